@@ -1,0 +1,314 @@
+"""The frictional-contact NCP of Section II.B (eq. NCP), plain FP64 numpy.
+
+For contact i with impulse Lam_i = (T1, T2, N) and velocity
+sigma_i = (G Lam + g)_i:
+
+    K_mu  contains Lam_i  _|_  sigma_i + Gamma(sigma_i)  in K_mu* = K_{1/mu},
+    Gamma(sigma) = (0, 0, mu |sigma_T|),
+
+which is the Signorini condition, the Coulomb cone and maximum dissipation.
+Lam is an impulse (force times dt), so G = J M^-1 J^T and v+ = v_f + M^-1 J^T Lam.
+
+Solver (Section II.B lists projected Gauss-Seidel among valid solvers; the
+derivative only depends on the solution):
+  1. block Gauss-Seidel over contacts with an exact local solve: separation
+     if the normal free velocity is non-negative, else the sticking impulse if
+     it lies in the cone, else the sliding impulse on the cone boundary with
+     sigma_N = 0 and Lam_T opposite to sigma_T (a 1-D root search over the
+     sliding direction);
+  2. Newton iterations on the equations of the realised modes (Section III.B:
+     breaking Lam = 0, sticking sigma = 0, sliding sigma_N = 0 and
+     Lam_T = -mu Lam_N sigma_T / |sigma_T|);
+  3. a check of every NCP condition.
+For at most three contacts, `enumerate_solutions` tries every assignment of
+modes and keeps each consistent solution (brute force).
+
+Pins (tests/test_oracle_ncp.py): single-contact closed forms for every mode,
+the conditions at every returned solution, agreement with brute force.
+"""
+from __future__ import annotations
+
+import itertools
+import numpy as np
+
+BRK, STK, SLD = 0, 1, 2
+
+
+def project_cone(x, mu):
+    """Euclidean projection onto K_mu = {|x_T| <= mu x_N}."""
+    xt, xn = x[:2], x[2]
+    nt = np.hypot(xt[0], xt[1])
+    if nt <= mu * xn:
+        return x.copy()
+    if mu * nt <= -xn:
+        return np.zeros(3)
+    beta = (mu * nt + xn) / (mu * mu + 1.0)
+    return np.array([mu * beta * xt[0] / nt, mu * beta * xt[1] / nt, beta])
+
+
+def desaxce(sig, mu):
+    return np.array([sig[0], sig[1], sig[2] + mu * np.hypot(sig[0], sig[1])])
+
+
+def natural_residual(G, g, mu, Lam):
+    """Per-contact |Lam_i - P_K(Lam_i - rho_i (sigma_i + Gamma(sigma_i)))| with
+    rho_i = 3 / trace(G_ii) (so that rho sigma is an impulse); zero iff the
+    NCP holds."""
+    nc = len(mu)
+    sig = G @ Lam + g
+    r = np.zeros(nc)
+    for i in range(nc):
+        s = slice(3 * i, 3 * i + 3)
+        tr = np.trace(G[s, s])
+        rho = 3.0 / tr if tr > 0 else 1.0
+        r[i] = np.linalg.norm(Lam[s] - project_cone(Lam[s] - rho * desaxce(sig[s], mu[i]), mu[i]))
+    return r
+
+
+# ---------------------------------------------------------------------------
+# single contact
+# ---------------------------------------------------------------------------
+
+def _slide_candidates(W, b, mu, nsample=720):
+    """All sliding solutions of the one-contact problem sigma = W Lam + b:
+    Lam = Lam_N (-mu t, 1), |t| = 1, sigma_N = 0, sigma_T = s t with s > 0.
+    The direction angle is sampled densely, sign changes of t x sigma_T are
+    refined by bisection."""
+    def parts(phi):
+        phi = np.atleast_1d(phi)
+        t = np.stack([np.cos(phi), np.sin(phi)], axis=-1)
+        den = W[2, 2] - mu * (t @ W[2, :2])
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ln = np.where(den > 0, -b[2] / den, np.nan)
+        lam = np.stack([-mu * ln * t[:, 0], -mu * ln * t[:, 1], ln], axis=-1)
+        st = lam @ W[:2, :].T + b[:2]
+        cr = t[:, 0] * st[:, 1] - t[:, 1] * st[:, 0]
+        return t, ln, lam, st, cr
+
+    phis = np.linspace(0.0, 2 * np.pi, nsample + 1)
+    vals = parts(phis)[4]
+    out = []
+    for k in range(nsample):
+        a, c = vals[k], vals[k + 1]
+        if not (np.isfinite(a) and np.isfinite(c)):
+            continue
+        if a == 0.0:
+            phi = phis[k]
+        elif a * c < 0:
+            lo, hi, flo = phis[k], phis[k + 1], a
+            for _ in range(80):
+                mid = 0.5 * (lo + hi)
+                fm = parts(mid)[4][0]
+                if not np.isfinite(fm):
+                    break
+                if flo * fm <= 0:
+                    hi = mid
+                else:
+                    lo, flo = mid, fm
+                if hi - lo < 1e-15:
+                    break
+            phi = 0.5 * (lo + hi)
+        else:
+            continue
+        t, ln, lam, st, _ = parts(phi)
+        if np.isfinite(ln[0]) and ln[0] > 0 and t[0] @ st[0] > 0:
+            out.append(lam[0])
+    return out
+
+
+def local_solve(W, b, mu):
+    """Exact solution of the one-contact NCP sigma = W Lam + b (W SPD).
+    Returns (Lam, mode)."""
+    if b[2] >= 0.0:
+        return np.zeros(3), BRK
+    lam = -np.linalg.solve(W, b)
+    if lam[2] > 0 and np.hypot(lam[0], lam[1]) <= mu * lam[2]:
+        return lam, STK
+    cands = _slide_candidates(W, b, mu)
+    if not cands:
+        # no consistent sliding root found: fall back to the cone projection
+        return project_cone(lam, mu), SLD
+    if len(cands) > 1:
+        # keep the candidate closest to the projected sticking impulse
+        ref = project_cone(lam, mu)
+        cands.sort(key=lambda c: np.linalg.norm(c - ref))
+    return cands[0], SLD
+
+
+# ---------------------------------------------------------------------------
+# mode-fixed Newton
+# ---------------------------------------------------------------------------
+
+def mode_equations(G, g, mu, Lam, modes):
+    """Residual of the equations of the given modes and its Jacobian in Lam."""
+    k = len(Lam)
+    sig = G @ Lam + g
+    F = np.zeros(k)
+    Jf = np.zeros((k, k))
+    for i, md in enumerate(modes):
+        s = slice(3 * i, 3 * i + 3)
+        if md == BRK:
+            F[s] = Lam[s]
+            Jf[s, s] = np.eye(3)
+        elif md == STK:
+            F[s] = sig[s]
+            Jf[s, :] = G[s, :]
+        else:
+            st = sig[3 * i:3 * i + 2]
+            ns = np.hypot(st[0], st[1])
+            u = st / ns
+            ln = Lam[3 * i + 2]
+            F[3 * i:3 * i + 2] = Lam[3 * i:3 * i + 2] + mu[i] * ln * u
+            F[3 * i + 2] = sig[3 * i + 2]
+            H = (np.eye(2) - np.outer(u, u)) / ns
+            rows = np.zeros((2, k))
+            rows[:, 3 * i:3 * i + 2] += np.eye(2)
+            rows[:, 3 * i + 2] += mu[i] * u
+            rows += mu[i] * ln * H @ G[3 * i:3 * i + 2, :]
+            Jf[3 * i:3 * i + 2, :] = rows
+            Jf[3 * i + 2, :] = G[3 * i + 2, :]
+    return F, Jf
+
+
+def newton_modes(G, g, mu, Lam, modes, iters=30):
+    Lam = Lam.copy()
+    best = None
+    for _ in range(iters):
+        F, Jf = mode_equations(G, g, mu, Lam, modes)
+        nf = np.linalg.norm(F)
+        if best is None or nf < best[0]:
+            best = (nf, Lam.copy())
+        if nf < 1e-300:
+            break
+        step = np.linalg.lstsq(Jf, -F, rcond=1e-13)[0]
+        # backtracking: halve the step until the residual decreases
+        t = 1.0
+        for _ in range(40):
+            Fn, _ = mode_equations(G, g, mu, Lam + t * step, modes)
+            if np.all(np.isfinite(Fn)) and np.linalg.norm(Fn) < nf:
+                break
+            t *= 0.5
+        else:
+            t = 1.0
+        step = t * step
+        Lam = Lam + step
+        if np.linalg.norm(step) <= 1e-16 * max(np.linalg.norm(Lam), 1e-300):
+            F, _ = mode_equations(G, g, mu, Lam, modes)
+            if np.linalg.norm(F) < best[0]:
+                best = (np.linalg.norm(F), Lam.copy())
+            break
+    return best[1]
+
+
+def classify(G, g, mu, Lam, eps=1e-9, dt=1e-3, gnorm=9.81):
+    """Contact modes of a solution (brk > stk > sld priority) and the
+    normalised margin to the nearest switching surface."""
+    nc = len(mu)
+    sig = G @ Lam + g
+    lam_n = np.array([Lam[3 * i + 2] for i in range(nc)])
+    s_lam = max(lam_n.max(initial=0.0), 1e-300)
+    s_sig = max(np.abs(g).max(initial=0.0), gnorm * dt)
+    modes = []
+    margin = np.inf
+    for i in range(nc):
+        ln = Lam[3 * i + 2]
+        nt_l = np.hypot(Lam[3 * i], Lam[3 * i + 1])
+        nt_s = np.hypot(sig[3 * i], sig[3 * i + 1])
+        sn = sig[3 * i + 2]
+        if ln <= eps * s_lam:
+            modes.append(BRK)
+            margin = min(margin, sn / s_sig)
+        elif nt_s <= eps * s_sig:
+            modes.append(STK)
+            margin = min(margin, ln / s_lam, (mu[i] * ln - nt_l) / s_lam)
+        else:
+            modes.append(SLD)
+            margin = min(margin, ln / s_lam, nt_s / s_sig)
+    return modes, margin
+
+
+def check(G, g, mu, Lam, tol=1e-9):
+    """Every NCP condition at Lam, relative to the problem's scales."""
+    nc = len(mu)
+    sig = G @ Lam + g
+    s_lam = max(np.abs(Lam).max(initial=0.0), 1e-300)
+    s_sig = max(np.abs(sig).max(initial=0.0), np.abs(g).max(initial=0.0), 1e-300)
+    ok = True
+    for i in range(nc):
+        L = Lam[3 * i:3 * i + 3]
+        S = sig[3 * i:3 * i + 3]
+        ok &= L[2] >= -tol * s_lam
+        ok &= np.hypot(L[0], L[1]) <= mu[i] * L[2] + tol * s_lam
+        ok &= S[2] >= -tol * s_sig
+        ok &= abs(L @ desaxce(S, mu[i])) <= tol * s_lam * s_sig
+        nt = np.hypot(S[0], S[1])
+        if nt > tol * s_sig and L[2] > tol * s_lam:
+            # sliding: Lam_T = -mu Lam_N sigma_T/|sigma_T|
+            ok &= np.linalg.norm(L[:2] + mu[i] * L[2] * S[:2] / nt) <= tol * s_lam * 10
+    return bool(ok)
+
+
+def solve(G, g, mu, tol=1e-12, max_sweeps=20000, Lam0=None):
+    """Solve the NCP. Returns (Lam, info)."""
+    nc = len(mu)
+    k = 3 * nc
+    Lam = np.zeros(k) if Lam0 is None else Lam0.copy()
+    info = dict(sweeps=0, polished=False, ok=False)
+    if nc == 0:
+        info["ok"] = True
+        return Lam, info
+    sweeps_done = 0
+    chunk = 50
+    while sweeps_done < max_sweeps:
+        for _ in range(chunk):
+            lmodes = []
+            for i in range(nc):
+                s = slice(3 * i, 3 * i + 3)
+                b = g[s] + G[s, :] @ Lam - G[s, s] @ Lam[s]
+                Lam[s], md = local_solve(G[s, s], b, mu[i])
+                lmodes.append(md)
+            sweeps_done += 1
+        # Newton on the realised modes, then verify
+        cand = newton_modes(G, g, mu, Lam, lmodes)
+        lam_scale = max(np.abs(cand).max(), 1e-300)
+        if check(G, g, mu, cand, tol=1e-11) and \
+                natural_residual(G, g, mu, cand).max() <= 1e-11 * lam_scale:
+            info.update(sweeps=sweeps_done, polished=True, ok=True)
+            return cand, info
+        r = natural_residual(G, g, mu, Lam).max()
+        if r <= tol * max(np.abs(Lam).max(), 1e-300) and check(G, g, mu, Lam, tol=1e-9):
+            info.update(sweeps=sweeps_done, ok=True)
+            return Lam, info
+        chunk = min(2 * chunk, 2000)
+    info.update(sweeps=sweeps_done, ok=check(G, g, mu, Lam, tol=1e-6))
+    return Lam, info
+
+
+def enumerate_solutions(G, g, mu, starts=24, seed=0):
+    """Brute force for small problems: every mode assignment, damped Newton
+    from several starts (random sliding directions), keep consistent
+    solutions (deduplicated)."""
+    nc = len(mu)
+    assert nc <= 3
+    rng = np.random.default_rng(seed)
+    sols = []
+    for modes in itertools.product((BRK, STK, SLD), repeat=nc):
+        for s in range(starts if SLD in modes else 1):
+            Lam = np.zeros(3 * nc)
+            for i in range(nc):
+                ang = rng.uniform(0, 2 * np.pi)
+                Lam[3 * i:3 * i + 3] = [0.9 * mu[i] * np.cos(ang), 0.9 * mu[i] * np.sin(ang), 1.0]
+            scale = max(np.abs(g).max(), 1e-12) / max(np.trace(G) / len(g), 1e-12)
+            Lam *= scale
+            try:
+                sol = newton_modes(G, g, mu, Lam, list(modes), iters=60)
+            except np.linalg.LinAlgError:
+                continue
+            F, _ = mode_equations(G, g, mu, sol, list(modes))
+            if not np.all(np.isfinite(F)) or np.linalg.norm(F) > 1e-10 * max(1.0, scale):
+                continue
+            if not check(G, g, mu, sol, tol=1e-9):
+                continue
+            if not any(np.linalg.norm(sol - o) <= 1e-8 * max(1.0, np.linalg.norm(o)) for o in sols):
+                sols.append(sol)
+    return sols
