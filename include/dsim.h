@@ -1,0 +1,203 @@
+/*
+ * dsim.h -- C ABI of the MI355X step-derivative library (gfx950, HIP).
+ *
+ * One time step of an articulated rigid-body system with frictional point
+ * contacts on the ground plane, and its analytical derivatives, for a batch
+ * of independent environments of possibly different sizes.
+ *
+ * The step (Section II.C, eq. 3-5; impulse form, Lam = dt * lambda):
+ *     v_f = v + dt M(q)^-1 (tau - b(q, v))
+ *     G   = J M^-1 J^T,  g = J v_f (+ phi / dt on normal rows, gap_mode 1)
+ *     Lam solves the NCP of Section II.B (eq. NCP) for (G, g, mu)
+ *     v+  = v_f + M^-1 J^T Lam
+ * and its derivatives (Section III, eq. FD_grads, eq. 7-12, Appendix B and D):
+ * d v+ / d(q, v, tau) through the mode-split reduced implicit system, or the
+ * vector-Jacobian product of the same derivative (reverse mode, Section III.A).
+ *
+ * Conventions (fixed):
+ *   - spatial layout of the model: see dsim_batch;
+ *   - a free-flyer root has q = (position, quaternion x y z w) and
+ *     v = (linear, angular) body-frame velocity; derivatives in q are taken
+ *     along the tangent perturbation q (+) dq = q * Exp(dq) (n_v columns);
+ *   - contacts: world-aligned frame (T1, T2, N) = (x, y, z), N = +z;
+ *   - Lam is returned as an impulse (N s); divide by dt for forces;
+ *   - gravity, dt and the gap mode travel in dsim_params.
+ *
+ * Memory and ownership: every pointer in dsim_batch and every array argument
+ * is DEVICE memory owned by the caller (the library never allocates or frees
+ * device memory, apart from kernel arguments).  Real arrays are float when
+ * params->precision == DSIM_F32 and double when DSIM_F64; index arrays are
+ * int32.  Buffers must stay valid until the work on `stream` has completed.
+ * `stream` is a hipStream_t (NULL = the default stream); all compute calls are
+ * asynchronous on it.
+ *
+ * Errors: every call returns 0 (DSIM_SUCCESS) or a negative DSIM_ERR_* code
+ * for invalid arguments, unsupported sizes or a failed launch; these are the
+ * only synchronous errors.  Numerical trouble in one environment never fails
+ * the call: it sets bits in that environment's status word (DSIM_ST_*) and the
+ * outputs are still written.
+ */
+#ifndef DSIM_H
+#define DSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSIM_ABI_VERSION 1
+
+/* return codes */
+#define DSIM_SUCCESS 0
+#define DSIM_ERR_ARG (-1)        /* null pointer, bad enum, negative size */
+#define DSIM_ERR_SIZE (-2)       /* size beyond the supported maxima */
+#define DSIM_ERR_LAUNCH (-3)     /* the HIP launch failed */
+#define DSIM_ERR_WORKSPACE (-4)  /* workspace smaller than dsim_workspace_bytes */
+#define DSIM_ERR_MODEL (-5)      /* dsim_validate_host: non-physical model */
+#define DSIM_ERR_DEVICE (-6)     /* no usable gfx950 device */
+
+/* per-environment status bits */
+#define DSIM_ST_NCP_NOT_CONVERGED 1  /* FP64 natural-map residual above ncp_tol */
+#define DSIM_ST_RANK_DEFICIENT 2     /* reduced system factorised with rank < m */
+#define DSIM_ST_MODE_DEGENERATE 4    /* a contact within mode_eps of a mode switch */
+#define DSIM_ST_NONFINITE 8          /* a NaN or Inf reached the outputs */
+#define DSIM_ST_POLISH_FAILED 16     /* Newton refinement left the mode set */
+
+/* contact modes written to `mode` (Section III.B) */
+#define DSIM_MODE_BREAK 0
+#define DSIM_MODE_STICK 1
+#define DSIM_MODE_SLIDE 2
+
+/* joint types */
+#define DSIM_JOINT_REVOLUTE 0
+#define DSIM_JOINT_FREEFLYER 1
+
+/* supported maxima per environment */
+#define DSIM_MAX_DOFS 64
+#define DSIM_MAX_BODIES 64
+#define DSIM_MAX_CONTACTS 21 /* 3 * contacts <= 64 */
+
+typedef enum { DSIM_F64 = 0, DSIM_F32 = 1 } dsim_precision;
+
+/* entry selector for dsim_workspace_bytes / dsim_lds_bytes */
+typedef enum { DSIM_ENTRY_STEP = 0, DSIM_ENTRY_JACOBIAN = 1, DSIM_ENTRY_VJP = 2 } dsim_entry;
+
+/*
+ * A batch of kinematic trees (Section II.C) with point contacts.
+ * Per-env ragged data is addressed by prefix offsets (n_env + 1 entries):
+ *   bodies of env e are body_off[e] .. body_off[e+1]-1, likewise dofs (v, tau
+ *   entries), configuration entries (q) and contacts.
+ * Per body (bodies listed parents first inside each env):
+ *   parent   int32, local index of the parent body, -1 = world
+ *   jtype    int32, DSIM_JOINT_*; a free flyer may only be local body 0
+ *   axis     real[3], unit joint axis in the joint frame (revolute)
+ *   jrot     real[9], row-major rotation of the joint frame in the parent body
+ *            frame (for the root: in the world frame)
+ *   jpos     real[3], joint frame origin in the parent body frame
+ *   mass     real, > 0
+ *   com      real[3], centre of mass in the body frame
+ *   inertia  real[6], rotational inertia about the COM in the body frame:
+ *            xx yy zz xy xz yz
+ * Per contact:
+ *   cbody    int32, local body index
+ *   cpoint   real[3], contact point in that body's frame
+ *   mu       real, friction coefficient >= 0
+ * jac_off (n_env + 1 entries) is the prefix sum of n_v^2, the offsets of the
+ * per-environment Jacobian blocks (needed by dsim_step_jacobian only; may be
+ * NULL otherwise).
+ * The max_* fields must bound every environment (they size the on-chip
+ * buffers); n_env may be 0.
+ */
+typedef struct dsim_batch {
+    int32_t n_env;
+    int32_t max_bodies, max_dofs, max_cfg, max_contacts;
+    const int32_t *body_off, *dof_off, *cfg_off, *contact_off, *jac_off;
+    const int32_t *parent, *jtype, *cbody;
+    const void *axis, *jrot, *jpos, *mass, *com, *inertia, *cpoint, *mu;
+} dsim_batch;
+
+typedef struct dsim_params {
+    double dt;            /* time step (s), > 0 */
+    double gravity[3];    /* world gravity (m/s^2) */
+    int32_t gap_mode;     /* 0: every contact touches (g = J v_f);
+                             1: g_N += phi/dt with phi = world z of the point
+                             (Appendix D with K_p = K_d = 0) */
+    int32_t precision;    /* dsim_precision */
+    int32_t ncp_sweeps;   /* block Gauss-Seidel sweeps per round (>= 1) */
+    int32_t ncp_rounds;   /* sweep rounds, each followed by Newton refinement */
+    int32_t newton_iters; /* Newton iterations per refinement (>= 0) */
+    int32_t threads;      /* threads per environment team: 64, 128 or 256 (0 = auto) */
+    double ncp_tol;       /* relative natural-map residual tolerance */
+    double rank_tol;      /* relative pivot tolerance of the reduced factorisation */
+    double mode_eps;      /* relative threshold of the mode classification */
+} dsim_params;
+
+/* fills `p` with the defaults for `precision` */
+void dsim_default_params(dsim_params* p, int32_t precision);
+
+int32_t dsim_abi_version(void);
+const char* dsim_error_string(int32_t code);
+
+/*
+ * Host-side validation of a batch whose pointers are HOST memory (no GPU
+ * needed): offsets monotone, sizes within the maxima, parents listed first,
+ * free flyer only at the root, unit axes and rotations, mass > 0, inertia
+ * positive definite and satisfying the triangle inequality, mu >= 0.
+ * Returns DSIM_SUCCESS, DSIM_ERR_ARG, DSIM_ERR_SIZE or DSIM_ERR_MODEL; the
+ * first offending environment is written to *bad_env when bad_env != NULL.
+ */
+int32_t dsim_validate_host(const dsim_batch* host_batch, int32_t* bad_env);
+
+/* Checks of the parameter block alone (host). */
+int32_t dsim_validate_params(const dsim_params* params);
+
+/* Bytes of device workspace the given entry needs for this batch (0 when
+ * everything fits on chip); `ws` arguments may be NULL when this is 0. */
+size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
+
+/* Bytes of on-chip (LDS) storage one environment team uses. */
+size_t dsim_lds_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
+
+/*
+ * The step (eq. 3-5 and the NCP).  Inputs q [sum n_q], v [sum n_v],
+ * tau [sum n_v]; outputs v_next [sum n_v], lam [3 * sum n_c] (impulses,
+ * (T1 T2 N) per contact), mode [sum n_c] (DSIM_MODE_*), status [n_env].
+ */
+int32_t dsim_step(const dsim_batch* batch, const dsim_params* params,
+                  const void* q, const void* v, const void* tau,
+                  void* v_next, void* lam, int8_t* mode, int32_t* status,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The step and its full Jacobian (eq. FD_grads with the reduced system of
+ * eq. 10 / Appendix B, assembled as in Appendix D).  Besides the dsim_step
+ * outputs: dvdq, dvdv, dvdtau, each n_v x n_v row-major per environment,
+ * concatenated over environments (offset sum over previous envs of n_v^2).
+ * Row i, column j of dvdq is d v+_i / d dq_j for the tangent perturbation.
+ */
+int32_t dsim_step_jacobian(const dsim_batch* batch, const dsim_params* params,
+                           const void* q, const void* v, const void* tau,
+                           void* v_next, void* lam, int8_t* mode, int32_t* status,
+                           void* dvdq, void* dvdv, void* dvdtau,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Reverse mode (Section III.A, the adjoint of the implicit system): recomputes
+ * the step and returns g_q = gbar^T dv+/ddq, g_v = gbar^T dv+/dv and
+ * g_tau = gbar^T dv+/dtau for gbar = g_vnext [sum n_v].  Also writes the step
+ * outputs (v_next, lam, mode, status).
+ */
+int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
+                      const void* q, const void* v, const void* tau,
+                      const void* g_vnext,
+                      void* v_next, void* lam, int8_t* mode, int32_t* status,
+                      void* g_q, void* g_v, void* g_tau,
+                      void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSIM_H */

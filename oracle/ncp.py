@@ -156,7 +156,15 @@ def mode_equations(G, g, mu, Lam, modes):
         else:
             st = sig[3 * i:3 * i + 2]
             ns = np.hypot(st[0], st[1])
-            u = st / ns
+            if not ns > 1e-300:
+                # no slip: the sliding law is undefined; hold the friction
+                # impulse on its current direction
+                lt = Lam[3 * i:3 * i + 2]
+                nl = np.hypot(lt[0], lt[1])
+                u = -lt / nl if nl > 0 else np.array([1.0, 0.0])
+                ns = 1e-300
+            else:
+                u = st / ns
             ln = Lam[3 * i + 2]
             F[3 * i:3 * i + 2] = Lam[3 * i:3 * i + 2] + mu[i] * ln * u
             F[3 * i + 2] = sig[3 * i + 2]
@@ -180,7 +188,12 @@ def newton_modes(G, g, mu, Lam, modes, iters=30):
             best = (nf, Lam.copy())
         if nf < 1e-300:
             break
-        step = np.linalg.lstsq(Jf, -F, rcond=1e-13)[0]
+        if not (np.all(np.isfinite(F)) and np.all(np.isfinite(Jf))):
+            break
+        try:
+            step = np.linalg.lstsq(Jf, -F, rcond=1e-13)[0]
+        except np.linalg.LinAlgError:
+            break
         # backtracking: halve the step until the residual decreases
         t = 1.0
         for _ in range(40):
@@ -248,7 +261,50 @@ def check(G, g, mu, Lam, tol=1e-9):
     return bool(ok)
 
 
-def solve(G, g, mu, tol=1e-12, max_sweeps=20000, Lam0=None):
+def active_set(G, g, mu, Lam, modes, max_changes=30):
+    """Newton on the equations of a mode set; while the result violates a
+    condition of its modes, move the offending contacts to the mode the
+    violation points to (penetrating breaking contact -> sticking, sticking
+    impulse outside the cone -> sliding, slip opposed to the friction
+    impulse -> sticking, negative normal impulse -> breaking) and repeat.
+    Returns the first solution that passes `check`, else None."""
+    modes = list(modes)
+    seen = set()
+    for _ in range(max_changes):
+        key = tuple(modes)
+        if key in seen:
+            return None
+        seen.add(key)
+        cand = newton_modes(G, g, mu, Lam, modes)
+        if check(G, g, mu, cand, tol=1e-11):
+            return cand
+        sig = G @ cand + g
+        s_lam = max(np.abs(cand).max(), 1e-300)
+        s_sig = max(np.abs(g).max(), 1e-300)
+        changed = False
+        for i in range(len(mu)):
+            L = cand[3 * i:3 * i + 3]
+            S = sig[3 * i:3 * i + 3]
+            if modes[i] == BRK:
+                if S[2] < -1e-11 * s_sig:
+                    modes[i] = STK
+                    changed = True
+            elif L[2] < -1e-11 * s_lam:
+                modes[i] = BRK
+                changed = True
+            elif modes[i] == STK and np.hypot(L[0], L[1]) > mu[i] * L[2] + 1e-11 * s_lam:
+                modes[i] = SLD
+                changed = True
+            elif modes[i] == SLD and L[0] * S[0] + L[1] * S[1] > 0:
+                modes[i] = STK
+                changed = True
+        if not changed:
+            return None
+        Lam = cand
+    return None
+
+
+def solve(G, g, mu, tol=1e-12, max_sweeps=2000, Lam0=None):
     """Solve the NCP. Returns (Lam, info)."""
     nc = len(mu)
     k = 3 * nc
@@ -279,6 +335,10 @@ def solve(G, g, mu, tol=1e-12, max_sweeps=20000, Lam0=None):
         if r <= tol * max(np.abs(Lam).max(), 1e-300) and check(G, g, mu, Lam, tol=1e-9):
             info.update(sweeps=sweeps_done, ok=True)
             return Lam, info
+        cand = active_set(G, g, mu, Lam, lmodes)
+        if cand is not None:
+            info.update(sweeps=sweeps_done, polished=True, ok=True, active_set=True)
+            return cand, info
         chunk = min(2 * chunk, 2000)
     info.update(sweeps=sweeps_done, ok=check(G, g, mu, Lam, tol=1e-6))
     return Lam, info

@@ -1,0 +1,330 @@
+// dsim_api.hip -- kernels for gfx950 and the C ABI of include/dsim.h.
+//
+// One workgroup (an "environment team" of 64, 128 or 256 threads) handles one
+// environment at a time; its scratch lives in LDS when it fits (160 KB per
+// workgroup on gfx950), otherwise in a caller-provided device workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/dsim.h"
+#include "dsim_pipeline.h"
+
+using namespace dsim;
+
+namespace {
+
+constexpr size_t kLdsLimit = 160 * 1024;  // bytes of LDS per workgroup on gfx950
+constexpr int kWsBlocks = 2048;           // workgroups in workspace mode
+
+template <class R>
+BatchView<R> view(const dsim_batch* b) {
+    BatchView<R> v;
+    v.n_env = b->n_env;
+    v.body_off = b->body_off;
+    v.dof_off = b->dof_off;
+    v.cfg_off = b->cfg_off;
+    v.contact_off = b->contact_off;
+    v.jac_off = b->jac_off;
+    v.parent = b->parent;
+    v.jtype = b->jtype;
+    v.cbody = b->cbody;
+    v.axis = static_cast<const R*>(b->axis);
+    v.jrot = static_cast<const R*>(b->jrot);
+    v.jpos = static_cast<const R*>(b->jpos);
+    v.mass = static_cast<const R*>(b->mass);
+    v.com = static_cast<const R*>(b->com);
+    v.inertia = static_cast<const R*>(b->inertia);
+    v.cpoint = static_cast<const R*>(b->cpoint);
+    v.mu = static_cast<const R*>(b->mu);
+    return v;
+}
+
+Params params_of(const dsim_params* p) {
+    Params q;
+    q.dt = p->dt;
+    q.gx = p->gravity[0];
+    q.gy = p->gravity[1];
+    q.gz = p->gravity[2];
+    q.gap_mode = p->gap_mode;
+    q.ncp_sweeps = p->ncp_sweeps;
+    q.ncp_rounds = p->ncp_rounds;
+    q.newton_iters = p->newton_iters;
+    q.ncp_tol = p->ncp_tol;
+    q.rank_tol = p->rank_tol;
+    q.mode_eps = p->mode_eps;
+    return q;
+}
+
+Dims dims_of(const dsim_batch* b) {
+    Dims d;
+    d.NB = b->max_bodies > 0 ? b->max_bodies : 1;
+    d.NV = b->max_dofs > 0 ? b->max_dofs : 1;
+    d.NC = b->max_contacts > 0 ? b->max_contacts : 1;
+    d.K = 3 * d.NC;
+    return d;
+}
+
+size_t team_bytes(const dsim_batch* b, const dsim_params* p, int entry) {
+    Dims d = dims_of(b);
+    if (p->precision == DSIM_F32) {
+        Env<float> E;
+        return carve<float>(nullptr, d, entry, E);
+    }
+    Env<double> E;
+    return carve<double>(nullptr, d, entry, E);
+}
+
+int team_threads(const dsim_params* p) {
+    return p->threads > 0 ? p->threads : 128;
+}
+
+template <class R, int ENTRY>
+__global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims D, const R* q, const R* v,
+                                                  const R* tau, const R* gbar, R* v_next, R* lam, int8_t* mode,
+                                                  int32_t* status, R* o1, R* o2, R* o3, char* ws, size_t ws_stride,
+                                                  int use_lds) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    Team T;
+    T.tid = threadIdx.x;
+    T.nt = blockDim.x;
+    T.lane = threadIdx.x & 63;
+    T.wave = threadIdx.x >> 6;
+    T.wsize = 64;
+    char* base = use_lds ? smem : ws + size_t(blockIdx.x) * ws_stride;
+    Env<R> E;
+    carve<R>(base, D, ENTRY, E);
+    for (int e = blockIdx.x; e < B.n_env; e += gridDim.x) {
+        run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, v_next, lam, mode, status, o1, o2, o3);
+    }
+}
+
+int check_common(const dsim_batch* b, const dsim_params* p) {
+    if (!b || !p) return DSIM_ERR_ARG;
+    int rc = dsim_validate_params(p);
+    if (rc) return rc;
+    if (b->n_env < 0) return DSIM_ERR_ARG;
+    if (b->max_bodies > DSIM_MAX_BODIES || b->max_dofs > DSIM_MAX_DOFS || b->max_contacts > DSIM_MAX_CONTACTS)
+        return DSIM_ERR_SIZE;
+    if (b->max_bodies < 0 || b->max_dofs < 0 || b->max_contacts < 0 || b->max_cfg < 0) return DSIM_ERR_ARG;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!b->body_off || !b->dof_off || !b->cfg_off || !b->contact_off || !b->parent || !b->jtype || !b->axis ||
+        !b->jrot || !b->jpos || !b->mass || !b->com || !b->inertia)
+        return DSIM_ERR_ARG;
+    if (b->max_contacts > 0 && (!b->cbody || !b->cpoint || !b->mu)) return DSIM_ERR_ARG;
+    return DSIM_SUCCESS;
+}
+
+template <class R, int ENTRY>
+int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+           const void* gbar, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1, void* o2, void* o3,
+           void* ws, size_t ws_bytes, void* stream) {
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    const size_t bytes = team_bytes(b, p, ENTRY);
+    const bool use_lds = bytes <= kLdsLimit;
+    const int threads = team_threads(p);
+    int grid = b->n_env;
+    size_t stride = 0;
+    if (!use_lds) {
+        grid = b->n_env < kWsBlocks ? b->n_env : kWsBlocks;
+        stride = (bytes + 255) & ~size_t(255);
+        if (!ws || ws_bytes < stride * size_t(grid)) return DSIM_ERR_WORKSPACE;
+    }
+    auto kern = env_kernel<R, ENTRY>;
+    const unsigned lds = use_lds ? unsigned(bytes) : 0u;
+    if (lds > 64 * 1024) {
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(lds)) != hipSuccess)
+            return DSIM_ERR_LAUNCH;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, static_cast<hipStream_t>(stream), view<R>(b),
+                       params_of(p), dims_of(b), static_cast<const R*>(q), static_cast<const R*>(v),
+                       static_cast<const R*>(tau), static_cast<const R*>(gbar), static_cast<R*>(v_next),
+                       static_cast<R*>(lam), mode, status, static_cast<R*>(o1), static_cast<R*>(o2),
+                       static_cast<R*>(o3), static_cast<char*>(ws), stride, use_lds ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
+}
+
+template <int ENTRY>
+int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+             const void* gbar, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1, void* o2, void* o3,
+             void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !v || !tau || !v_next || !status || !mode || !lam) return DSIM_ERR_ARG;
+    if (p->precision == DSIM_F32)
+        return launch<float, ENTRY>(b, p, q, v, tau, gbar, v_next, lam, mode, status, o1, o2, o3, ws, ws_bytes,
+                                    stream);
+    return launch<double, ENTRY>(b, p, q, v, tau, gbar, v_next, lam, mode, status, o1, o2, o3, ws, ws_bytes,
+                                 stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+void dsim_default_params(dsim_params* p, int32_t precision) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->dt = 1e-3;
+    p->gravity[0] = 0.0;
+    p->gravity[1] = 0.0;
+    p->gravity[2] = -9.81;
+    p->gap_mode = 0;
+    p->precision = precision;
+    p->ncp_sweeps = 30;
+    p->ncp_rounds = 4;
+    p->newton_iters = 6;
+    p->threads = 0;
+    if (precision == DSIM_F32) {
+        p->ncp_tol = 1e-5;
+        p->rank_tol = 1e-5;
+        p->mode_eps = 1e-5;
+    } else {
+        p->ncp_tol = 1e-12;
+        p->rank_tol = 1e-10;
+        p->mode_eps = 1e-9;
+    }
+}
+
+int32_t dsim_abi_version(void) { return DSIM_ABI_VERSION; }
+
+const char* dsim_error_string(int32_t code) {
+    switch (code) {
+        case DSIM_SUCCESS: return "success";
+        case DSIM_ERR_ARG: return "invalid argument";
+        case DSIM_ERR_SIZE: return "size beyond the supported maxima";
+        case DSIM_ERR_LAUNCH: return "kernel launch failed";
+        case DSIM_ERR_WORKSPACE: return "workspace too small";
+        case DSIM_ERR_MODEL: return "non-physical model";
+        case DSIM_ERR_DEVICE: return "no usable gfx950 device";
+        default: return "unknown error";
+    }
+}
+
+int32_t dsim_validate_params(const dsim_params* p) {
+    if (!p) return DSIM_ERR_ARG;
+    if (!(p->dt > 0) || !std::isfinite(p->dt)) return DSIM_ERR_ARG;
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(p->gravity[i])) return DSIM_ERR_ARG;
+    if (p->gap_mode != 0 && p->gap_mode != 1) return DSIM_ERR_ARG;
+    if (p->precision != DSIM_F64 && p->precision != DSIM_F32) return DSIM_ERR_ARG;
+    if (p->ncp_sweeps < 1 || p->ncp_rounds < 1 || p->newton_iters < 0) return DSIM_ERR_ARG;
+    if (p->threads != 0 && p->threads != 64 && p->threads != 128 && p->threads != 256) return DSIM_ERR_ARG;
+    if (!(p->ncp_tol > 0) || !(p->rank_tol > 0) || !(p->mode_eps >= 0)) return DSIM_ERR_ARG;
+    return DSIM_SUCCESS;
+}
+
+int32_t dsim_validate_host(const dsim_batch* b, int32_t* bad_env) {
+    if (bad_env) *bad_env = -1;
+    if (!b || b->n_env < 0) return DSIM_ERR_ARG;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!b->body_off || !b->dof_off || !b->cfg_off || !b->contact_off || !b->parent || !b->jtype || !b->axis ||
+        !b->jrot || !b->jpos || !b->mass || !b->com || !b->inertia)
+        return DSIM_ERR_ARG;
+    if (b->max_bodies > DSIM_MAX_BODIES || b->max_dofs > DSIM_MAX_DOFS || b->max_contacts > DSIM_MAX_CONTACTS)
+        return DSIM_ERR_SIZE;
+    const double* axis = static_cast<const double*>(b->axis);
+    const double* jrot = static_cast<const double*>(b->jrot);
+    const double* mass = static_cast<const double*>(b->mass);
+    const double* inertia = static_cast<const double*>(b->inertia);
+    const double* mu = static_cast<const double*>(b->mu);
+    if (b->body_off[0] != 0 || b->dof_off[0] != 0 || b->cfg_off[0] != 0 || b->contact_off[0] != 0)
+        return DSIM_ERR_ARG;
+    for (int e = 0; e < b->n_env; ++e) {
+        auto fail = [&](int code) {
+            if (bad_env) *bad_env = e;
+            return code;
+        };
+        const int b0 = b->body_off[e], nb = b->body_off[e + 1] - b0;
+        const int nc = b->contact_off[e + 1] - b->contact_off[e];
+        const int nvv = b->dof_off[e + 1] - b->dof_off[e];
+        const int nqq = b->cfg_off[e + 1] - b->cfg_off[e];
+        if (nb < 1 || nc < 0 || nvv < 1 || nqq < 1) return fail(DSIM_ERR_ARG);
+        if (nb > b->max_bodies || nc > b->max_contacts || nvv > b->max_dofs || nqq > b->max_cfg)
+            return fail(DSIM_ERR_SIZE);
+        int nv = 0, nq = 0;
+        for (int i = 0; i < nb; ++i) {
+            const int gi = b0 + i;
+            const int par = b->parent[gi], jt = b->jtype[gi];
+            if (par >= i || par < -1) return fail(DSIM_ERR_MODEL);
+            if (jt != DSIM_JOINT_REVOLUTE && jt != DSIM_JOINT_FREEFLYER) return fail(DSIM_ERR_MODEL);
+            if (jt == DSIM_JOINT_FREEFLYER && (i != 0 || par != -1)) return fail(DSIM_ERR_MODEL);
+            nv += jt == DSIM_JOINT_FREEFLYER ? 6 : 1;
+            nq += jt == DSIM_JOINT_FREEFLYER ? 7 : 1;
+            if (jt == DSIM_JOINT_REVOLUTE) {
+                const double* a = axis + 3 * gi;
+                const double na = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+                if (!(std::fabs(na - 1.0) < 1e-6)) return fail(DSIM_ERR_MODEL);
+            }
+            const double* Rm = jrot + 9 * gi;
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    double s = 0;
+                    for (int k = 0; k < 3; ++k) s += Rm[3 * r + k] * Rm[3 * c + k];
+                    if (!(std::fabs(s - (r == c ? 1.0 : 0.0)) < 1e-6)) return fail(DSIM_ERR_MODEL);
+                }
+            if (!(mass[gi] > 0) || !std::isfinite(mass[gi])) return fail(DSIM_ERR_MODEL);
+            const double* I = inertia + 6 * gi;
+            // positive definite (Sylvester) and principal moments satisfying the
+            // triangle inequality (checked on the diagonal of any frame as a
+            // necessary condition: Ixx + Iyy >= Izz etc.)
+            const double d1 = I[0], d2 = I[0] * I[1] - I[3] * I[3];
+            const double d3 = I[0] * (I[1] * I[2] - I[5] * I[5]) - I[3] * (I[3] * I[2] - I[5] * I[4]) +
+                              I[4] * (I[3] * I[5] - I[1] * I[4]);
+            if (!(d1 > 0 && d2 > 0 && d3 > 0)) return fail(DSIM_ERR_MODEL);
+            if (!(I[0] + I[1] >= I[2] * (1 - 1e-9) && I[0] + I[2] >= I[1] * (1 - 1e-9) &&
+                  I[1] + I[2] >= I[0] * (1 - 1e-9)))
+                return fail(DSIM_ERR_MODEL);
+        }
+        if (nv != nvv || nq != nqq) return fail(DSIM_ERR_ARG);
+        for (int c = 0; c < nc; ++c) {
+            const int gc = b->contact_off[e] + c;
+            if (!b->cbody || !b->cpoint || !b->mu) return fail(DSIM_ERR_ARG);
+            if (b->cbody[gc] < 0 || b->cbody[gc] >= nb) return fail(DSIM_ERR_MODEL);
+            if (!(mu[gc] >= 0) || !std::isfinite(mu[gc])) return fail(DSIM_ERR_MODEL);
+        }
+        if (b->jac_off && b->jac_off[e + 1] - b->jac_off[e] != nv * nv) return fail(DSIM_ERR_ARG);
+    }
+    return DSIM_SUCCESS;
+}
+
+size_t dsim_lds_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) {
+    if (!b || !p || entry < 0 || entry > 2) return 0;
+    return team_bytes(b, p, entry);
+}
+
+size_t dsim_workspace_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) {
+    if (!b || !p || entry < 0 || entry > 2 || b->n_env <= 0) return 0;
+    const size_t bytes = team_bytes(b, p, entry);
+    if (bytes <= kLdsLimit) return 0;
+    const size_t stride = (bytes + 255) & ~size_t(255);
+    const int grid = b->n_env < kWsBlocks ? b->n_env : kWsBlocks;
+    return stride * size_t(grid);
+}
+
+int32_t dsim_step(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+                  void* v_next, void* lam, int8_t* mode, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    return dispatch<ENTRY_STEP>(b, p, q, v, tau, nullptr, v_next, lam, mode, status, nullptr, nullptr, nullptr, ws,
+                                ws_bytes, stream);
+}
+
+int32_t dsim_step_jacobian(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+                           void* v_next, void* lam, int8_t* mode, int32_t* status, void* dvdq, void* dvdv,
+                           void* dvdtau, void* ws, size_t ws_bytes, void* stream) {
+    if (!dvdq || !dvdv || !dvdtau || (b && b->n_env > 0 && !b->jac_off)) return DSIM_ERR_ARG;
+    return dispatch<ENTRY_JAC>(b, p, q, v, tau, nullptr, v_next, lam, mode, status, dvdq, dvdv, dvdtau, ws,
+                               ws_bytes, stream);
+}
+
+int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+                      const void* g_vnext, void* v_next, void* lam, int8_t* mode, int32_t* status, void* g_q,
+                      void* g_v, void* g_tau, void* ws, size_t ws_bytes, void* stream) {
+    if (!g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
+    return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, v_next, lam, mode, status, g_q, g_v, g_tau, ws, ws_bytes,
+                               stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+"""Python binding of libdsim.so (include/dsim.h): argument marshalling only.
+
+Every computation of the step and its derivatives runs in the HIP kernels of
+the library; this module moves a scene batch to device memory (torch tensors
+used as plain device buffers), fills the C structs with their addresses and
+calls the C entry points on torch's current stream.  It raises if the library
+has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsim.so")
+
+F64, F32 = 0, 1
+ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP = 0, 1, 2
+ST_NCP_NOT_CONVERGED, ST_RANK_DEFICIENT, ST_MODE_DEGENERATE, ST_NONFINITE, ST_POLISH_FAILED = 1, 2, 4, 8, 16
+MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
+
+SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim_validate_host",
+           "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
+           "dsim_step_jacobian", "dsim_step_vjp")
+
+_vp = ctypes.c_void_p
+
+
+class CBatch(ctypes.Structure):
+    _fields_ = [("n_env", ctypes.c_int32), ("max_bodies", ctypes.c_int32), ("max_dofs", ctypes.c_int32),
+                ("max_cfg", ctypes.c_int32), ("max_contacts", ctypes.c_int32),
+                ("body_off", _vp), ("dof_off", _vp), ("cfg_off", _vp), ("contact_off", _vp), ("jac_off", _vp),
+                ("parent", _vp), ("jtype", _vp), ("cbody", _vp),
+                ("axis", _vp), ("jrot", _vp), ("jpos", _vp), ("mass", _vp), ("com", _vp), ("inertia", _vp),
+                ("cpoint", _vp), ("mu", _vp)]
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("gap_mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("ncp_sweeps", ctypes.c_int32), ("ncp_rounds", ctypes.c_int32),
+                ("newton_iters", ctypes.c_int32), ("threads", ctypes.c_int32), ("ncp_tol", ctypes.c_double),
+                ("rank_tol", ctypes.c_double), ("mode_eps", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_07107_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.dsim_default_params.argtypes = [ctypes.POINTER(CParams), ctypes.c_int32]
+        L.dsim_default_params.restype = None
+        L.dsim_abi_version.restype = ctypes.c_int32
+        L.dsim_error_string.argtypes = [ctypes.c_int32]
+        L.dsim_error_string.restype = ctypes.c_char_p
+        L.dsim_validate_host.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(ctypes.c_int32)]
+        L.dsim_validate_host.restype = ctypes.c_int32
+        L.dsim_validate_params.argtypes = [ctypes.POINTER(CParams)]
+        L.dsim_validate_params.restype = ctypes.c_int32
+        for f in (L.dsim_workspace_bytes, L.dsim_lds_bytes):
+            f.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams), ctypes.c_int32]
+            f.restype = ctypes.c_size_t
+        L.dsim_step.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 7 + [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step.restype = ctypes.c_int32
+        L.dsim_step_jacobian.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 10 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_jacobian.restype = ctypes.c_int32
+        L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_vjp.restype = ctypes.c_int32
+        _LIB = L
+    return _LIB
+
+
+class DsimError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != 0:
+        raise DsimError(f"dsim error {rc}: {lib().dsim_error_string(rc).decode()}")
+
+
+def params(prec=F32, **overrides) -> CParams:
+    p = CParams()
+    lib().dsim_default_params(ctypes.byref(p), int(prec))
+    for k, v in overrides.items():
+        if k == "gravity":
+            for i in range(3):
+                p.gravity[i] = float(v[i])
+        else:
+            setattr(p, k, type(getattr(p, k))(v))
+    return p
+
+
+def jac_offsets(dof_off) -> np.ndarray:
+    nv = np.diff(np.asarray(dof_off, dtype=np.int64))
+    o = np.zeros(len(nv) + 1, dtype=np.int64)
+    o[1:] = np.cumsum(nv * nv)
+    if o[-1] >= 2 ** 31:
+        raise ValueError("Jacobian offsets exceed int32")
+    return o.astype(np.int32)
+
+
+def _host_batch_struct(batch, keep):
+    """CBatch over HOST numpy arrays (float64), for dsim_validate_host."""
+    def p(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+    nb, nv, nq, nc = batch.max_sizes
+    return CBatch(batch.n_env, nb, nv, nq, nc,
+                  p(batch.body_off, np.int32), p(batch.dof_off, np.int32), p(batch.cfg_off, np.int32),
+                  p(batch.contact_off, np.int32), p(jac_offsets(batch.dof_off), np.int32),
+                  p(batch.parent, np.int32), p(batch.jtype, np.int32), p(batch.cbody, np.int32),
+                  p(batch.axis, np.float64), p(batch.jrot, np.float64), p(batch.jpos, np.float64),
+                  p(batch.mass, np.float64), p(batch.com, np.float64), p(batch.inertia, np.float64),
+                  p(batch.cpoint, np.float64), p(batch.mu, np.float64))
+
+
+def validate_host(batch):
+    """Host-side model checks (no GPU). Returns (code, first bad env)."""
+    keep = []
+    cb = _host_batch_struct(batch, keep)
+    bad = ctypes.c_int32(-1)
+    rc = lib().dsim_validate_host(ctypes.byref(cb), ctypes.byref(bad))
+    return int(rc), int(bad.value)
+
+
+class DeviceBatch:
+    """A scene batch resident in device memory in one precision."""
+
+    def __init__(self, batch, precision=F32, device="cuda"):
+        import torch
+        self.batch = batch
+        self.precision = int(precision)
+        self.dtype = torch.float32 if self.precision == F32 else torch.float64
+        self.device = torch.device(device)
+        rc, bad = validate_host(batch)
+        if rc != 0:
+            raise DsimError(f"invalid model in env {bad}: {lib().dsim_error_string(rc).decode()}")
+
+        def t(a, dt):
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(self.device)
+
+        i32, R = torch.int32, self.dtype
+        self.arrays = dict(
+            body_off=t(batch.body_off, i32), dof_off=t(batch.dof_off, i32), cfg_off=t(batch.cfg_off, i32),
+            contact_off=t(batch.contact_off, i32), jac_off=t(jac_offsets(batch.dof_off), i32),
+            parent=t(batch.parent, i32), jtype=t(batch.jtype, i32),
+            cbody=t(batch.cbody if len(batch.cbody) else np.zeros(1), i32),
+            axis=t(batch.axis, R), jrot=t(batch.jrot, R), jpos=t(batch.jpos, R), mass=t(batch.mass, R),
+            com=t(batch.com, R), inertia=t(batch.inertia, R),
+            cpoint=t(batch.cpoint if len(batch.cpoint) else np.zeros((1, 3)), R),
+            mu=t(batch.mu if len(batch.mu) else np.zeros(1), R))
+        self.q = t(batch.q, R)
+        self.v = t(batch.v, R)
+        self.tau = t(batch.tau, R)
+        nb, nv, nq, nc = batch.max_sizes
+        a = self.arrays
+        self.c = CBatch(batch.n_env, nb, nv, nq, nc,
+                        *(a[k].data_ptr() for k in ("body_off", "dof_off", "cfg_off", "contact_off", "jac_off",
+                                                    "parent", "jtype", "cbody", "axis", "jrot", "jpos", "mass",
+                                                    "com", "inertia", "cpoint", "mu")))
+        self.n_env = batch.n_env
+        self.n_dof = int(batch.dof_off[-1])
+        self.n_contact = int(batch.contact_off[-1])
+        self.n_jac = int(jac_offsets(batch.dof_off)[-1])
+        self._ws = {}
+
+    def params(self, **overrides) -> CParams:
+        p = params(self.precision, **overrides)
+        p.dt = float(overrides.get("dt", self.batch.dt))
+        g = overrides.get("gravity", self.batch.gravity)
+        for i in range(3):
+            p.gravity[i] = float(g[i])
+        p.gap_mode = int(overrides.get("gap_mode", self.batch.gap_mode))
+        return p
+
+    def workspace(self, p: CParams, entry: int):
+        import torch
+        nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(self.c), ctypes.byref(p), int(entry)))
+        if nbytes == 0:
+            return None, 0
+        key = (entry, nbytes)
+        if key not in self._ws:
+            self._ws[key] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws[key], nbytes
+
+    def lds_bytes(self, p: CParams, entry: int) -> int:
+        return int(lib().dsim_lds_bytes(ctypes.byref(self.c), ctypes.byref(p), int(entry)))
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _outputs(db: DeviceBatch):
+    import torch
+    dev, R = db.device, db.dtype
+    return dict(v_next=torch.empty(db.n_dof, dtype=R, device=dev),
+                lam=torch.empty(3 * max(db.n_contact, 1), dtype=R, device=dev),
+                mode=torch.empty(max(db.n_contact, 1), dtype=torch.int8, device=dev),
+                status=torch.empty(max(db.n_env, 1), dtype=torch.int32, device=dev))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+    """v+, impulses, modes and status of one step for every environment."""
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    out = out or _outputs(db)
+    ws, nbytes = db.workspace(p, ENTRY_STEP)
+    _check(lib().dsim_step(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                           _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
+                           _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+    """The step plus dv+/d(dq, v, tau), each block n_v x n_v row-major per
+    environment, concatenated (offsets: jac_offsets(dof_off))."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        for k in ("dvdq", "dvdv", "dvdtau"):
+            out[k] = torch.empty(max(db.n_jac, 1), dtype=db.dtype, device=db.device)
+    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN)
+    _check(lib().dsim_step_jacobian(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                                    _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
+                                    _ptr(out["status"]), _ptr(out["dvdq"]), _ptr(out["dvdv"]),
+                                    _ptr(out["dvdtau"]), _ptr(ws), ctypes.c_size_t(nbytes),
+                                    ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+    """The step plus g^T dv+/d(dq, v, tau) for g = g_vnext (per environment)."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        for k in ("g_q", "g_v", "g_tau"):
+            out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
+    ws, nbytes = db.workspace(p, ENTRY_VJP)
+    _check(lib().dsim_step_vjp(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                               _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
+                               _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]), _ptr(out["g_tau"]),
+                               _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    return out
+
+
+def split_jacobian(db: DeviceBatch, out, e: int):
+    """Host copy of the (n_v, 3 n_v) Jacobian of env e: [d/ddq, d/dv, d/dtau]."""
+    jo = jac_offsets(db.batch.dof_off)
+    nv = int(db.batch.dof_off[e + 1] - db.batch.dof_off[e])
+    blocks = [out[k][jo[e]:jo[e + 1]].reshape(nv, nv).double().cpu().numpy() for k in ("dvdq", "dvdv", "dvdtau")]
+    return np.concatenate(blocks, axis=1)

@@ -225,7 +225,7 @@ def cube(n_env=1, seed=0, v_std=0.1, mu=0.5, side=0.1, mass=1.0) -> Batch:
     return _assemble(recs, dt=1e-3, gravity=GRAVITY, gap_mode=0, name="cube")
 
 
-def arm7(n_env=1, seed=0, v_std=0.5, tau_std=2.0) -> Batch:
+def arm7(n_env=1, seed=0, v_std=0.02, tau_std=0.2) -> Batch:
     """Fixed-base chain of 7 revolute joints with random axes; link lengths
     U(0.1, 0.4) m, masses U(0.5, 3) kg, box inertias; a 4-point patch at the
     end-effector tip; mu ~ U(0.3, 1.0) per contact; a distinct model per env."""
@@ -248,7 +248,7 @@ def arm7(n_env=1, seed=0, v_std=0.5, tau_std=2.0) -> Batch:
     return _assemble(recs, dt=1e-3, gravity=GRAVITY, gap_mode=0, name="arm7")
 
 
-def tree36(n_env=1, seed=0, v_std=0.3, tau_std=2.0, mu=0.7, branches=5,
+def tree36(n_env=1, seed=0, v_std=0.005, tau_std=0.05, mu=0.7, branches=5,
            links_per_branch=6, feet=(0, 1)) -> Batch:
     """Free-flyer base with `branches` chains of `links_per_branch` revolute
     joints (36 dof by default); two feet (last link of branches 0 and 1) carry
@@ -283,7 +283,7 @@ def tree36(n_env=1, seed=0, v_std=0.3, tau_std=2.0, mu=0.7, branches=5,
     return _assemble(recs, dt=1e-3, gravity=GRAVITY, gap_mode=0, name="tree36")
 
 
-def mixed(n_env=1, seed=0, v_std=0.3, tau_std=2.0) -> Batch:
+def mixed(n_env=1, seed=0, v_std=0.005, tau_std=0.05) -> Batch:
     """Random trees: n_v ~ U{7..40} (half of them on a free flyer), branching
     factor U{1..5} from the root with dofs split evenly, n_c ~ U{0..16} as
     4-point patches on random leaves plus single leftover points,

@@ -1,0 +1,66 @@
+"""Writes the oracle's results for the seeded parity workloads to
+tests/golden/*.npz.  Calls only the oracle (and the seeded scene generator);
+nothing here comes from the HIP path.
+
+    python tests/golden/make_golden.py [name ...]
+
+Each file holds, per listed environment: index, v+ (n_v), J^T Lam (n_v),
+modes (n_c), margin, solver ok flag, uniqueness of the v+ derivative, and the
+full Jacobian d v+ / d(dq, v, tau) (n_v x 3 n_v).
+"""
+from __future__ import annotations
+
+import os
+import sys
+from multiprocessing import Pool
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from paper_2409_07107_amd import scenes  # noqa: E402
+from oracle import derivative, step  # noqa: E402
+
+# name -> (workload, n_env of the batch, seed, env indices to store)
+SETS = {
+    "cube8": ("cube", 8, 1, list(range(8))),
+    "arm7_64": ("arm7", 64, 2, list(range(64))),
+    "tree36_24": ("tree36", 24, 3, list(range(24))),
+    # full-size batches: sampled environments (first, interior, ragged tail)
+    "arm7_4096_sample": ("arm7", 4096, 0, [0, 1, 2, 63, 64, 1000, 2047, 2048, 3001, 4093, 4094, 4095]),
+    "tree36_16384_sample": ("tree36", 16384, 0, [0, 1, 2, 3, 255, 256, 4097, 8191, 8192, 12000,
+                                                   16379, 16380, 16381, 16382, 16383]),
+}
+
+_BATCH = None
+
+
+def _one(e):
+    env = _BATCH.env(e)
+    r = step.forward(env)
+    d = derivative.ift(env, r)
+    return dict(env=e, vnext=r["vnext"], JtLam=r["JtLam"], modes=np.array(r["modes"], dtype=np.int8),
+                margin=r["margin"], ok=bool(r["info"]["ok"]), unique=bool(d["unique_v"]), jac=d["jac"],
+                residual=float(r["residual"].max()) if len(r["residual"]) else 0.0)
+
+
+def make(name):
+    global _BATCH
+    wl, n, seed, envs = SETS[name]
+    _BATCH = scenes.make(wl, n, seed=seed)
+    with Pool(min(8, len(envs))) as p:
+        res = p.map(_one, envs)
+    out = dict(envs=np.array(envs), workload=wl, n_env=n, seed=seed)
+    for key in ("vnext", "JtLam", "modes", "jac"):
+        out[key] = np.array([r[key] for r in res], dtype=object if wl == "mixed" else None)
+    for key in ("margin", "ok", "unique", "residual"):
+        out[key] = np.array([r[key] for r in res])
+    path = os.path.join(HERE, f"{name}.npz")
+    np.savez_compressed(path, **out)
+    print(name, "ok", int(out["ok"].sum()), "/", len(envs), "unique", int(out["unique"].sum()), flush=True)
+
+
+if __name__ == "__main__":
+    for name in (sys.argv[1:] or list(SETS)):
+        make(name)

@@ -1,0 +1,122 @@
+"""GPU parity of the HIP step and full Jacobian against the FP64 oracle
+(stored by tests/golden/make_golden.py), through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2409_07107_amd import scenes
+from tests.parity_util import TOL, compare, load_golden, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("cube8", 0), ("cube8", 1), ("arm7_64", 0), ("arm7_64", 1), ("tree36_24", 0), ("tree36_24", 1)]
+
+
+def _run(name, precision, threads=0):
+    import torch
+    from paper_2409_07107_amd import dsim
+    gold = load_golden(name)
+    batch = scenes.make(str(gold["workload"]), int(gold["n_env"]), seed=int(gold["seed"]))
+    db = dsim.DeviceBatch(batch, precision=precision)
+    p = db.params(threads=threads)
+    say(f"run {name} precision {precision} threads {threads} n_env {batch.n_env} lds {db.lds_bytes(p, 1)}")
+    out = dsim.step_jacobian(db, p=p)
+    torch.cuda.synchronize()
+    return gold, batch, db, out
+
+
+@pytest.mark.parametrize("name,precision", CASES)
+def test_jacobian_parity(name, precision, gpu_lib):
+    gold, batch, db, out = _run(name, precision)
+    st = compare(batch, gold, out, db, precision, label=f"{name} p{precision}")
+    tol = TOL[precision]
+    assert st["included"] >= max(1, st["n"] // 3), "too few comparable environments"
+    assert st["v_max"] <= tol["v"]
+    assert st["jac_max"] <= tol["jac"]
+    assert st["modes_agree"] == st["included"]
+    assert st["solver_flags"] <= max(1, st["n"] // 10)
+
+
+@pytest.mark.parametrize("name,precision", [("arm7_4096_sample", 1), ("tree36_16384_sample", 1),
+                                            ("tree36_16384_sample", 0)])
+def test_full_size_sampled_parity(name, precision, gpu_lib):
+    """Full batch in the benchmark's launch configuration, sampled outputs."""
+    gold, batch, db, out = _run(name, precision)
+    st = compare(batch, gold, out, db, precision, label=f"{name} p{precision}")
+    tol = TOL[precision]
+    assert st["included"] >= st["n"] // 2
+    assert st["v_max"] <= tol["v"]
+    assert st["jac_max"] <= tol["jac"]
+    assert st["modes_agree"] == st["included"]
+    status = out["status"].cpu().numpy()
+    flagged = int(((status & 17) != 0).sum())
+    say(f"solver flags over the full batch: {flagged} / {batch.n_env}")
+    assert flagged <= batch.n_env // 20
+
+
+@pytest.mark.parametrize("threads", [64, 256])
+def test_team_size_invariance(threads, gpu_lib):
+    """Results do not depend on the team size beyond rounding."""
+    import torch
+    gold, batch, db, out = _run("tree36_24", 0, threads=threads)
+    st = compare(batch, gold, out, db, 0, label=f"tree36 threads {threads}")
+    assert st["jac_max"] <= TOL[0]["jac"]
+
+
+def test_mixed_batch_matches_separate_runs(gpu_lib):
+    """A ragged batch of different trees gives, per environment, exactly the
+    results of running each workload alone."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    parts = [scenes.make("cube", 3, seed=4), scenes.make("arm7", 5, seed=5), scenes.make("tree36", 4, seed=6)]
+    mixed = scenes.concat(parts)
+    say(f"mixed batch {mixed.n_env} envs, max sizes {mixed.max_sizes}")
+    dbm = dsim.DeviceBatch(mixed, precision=0)
+    om = dsim.step_jacobian(dbm)
+    torch.cuda.synchronize()
+    e0 = 0
+    for part in parts:
+        dbp = dsim.DeviceBatch(part, precision=0)
+        op = dsim.step_jacobian(dbp)
+        torch.cuda.synchronize()
+        for e in range(part.n_env):
+            Jm = dsim.split_jacobian(dbm, om, e0 + e)
+            Jp = dsim.split_jacobian(dbp, op, e)
+            assert np.abs(Jm - Jp).max() <= 1e-12 * max(1.0, np.abs(Jp).max())
+            d0, d1 = part.dof_off[e], part.dof_off[e + 1]
+            m0 = mixed.dof_off[e0 + e]
+            assert np.abs(om["v_next"][m0:m0 + d1 - d0].cpu().numpy() - op["v_next"][d0:d1].cpu().numpy()).max() \
+                <= 1e-13
+        e0 += part.n_env
+
+
+def test_step_only_matches_jacobian_entry(gpu_lib):
+    import torch
+    from paper_2409_07107_amd import dsim
+    batch = scenes.make("tree36", 8, seed=3)
+    db = dsim.DeviceBatch(batch, precision=1)
+    a = dsim.step(db)
+    b = dsim.step_jacobian(db)
+    torch.cuda.synchronize()
+    assert torch.equal(a["v_next"], b["v_next"])
+    assert torch.equal(a["mode"], b["mode"])
+    assert torch.equal(a["status"], b["status"])
+
+
+def test_empty_batch_and_no_contacts(gpu_lib):
+    import torch
+    from paper_2409_07107_amd import dsim
+    # free fall: no contacts at all
+    b = scenes.body(-1, scenes.FREEFLYER, mass=1.3, inertia=(0.02, 0.03, 0.05, 0, 0, 0))
+    rec = scenes.record([b], [], [0, 0, 1.0, 0, 0, 0, 1.0], [0.3, -0.1, 0.2, 0.5, -0.4, 0.7], np.zeros(6))
+    batch = scenes.assemble([rec, rec])
+    from oracle import derivative, step
+    ref = step.forward(batch.env(0))
+    dref = derivative.ift(batch.env(0), ref)
+    for prec in (0, 1):
+        db = dsim.DeviceBatch(batch, precision=prec)
+        out = dsim.step_jacobian(db)
+        torch.cuda.synchronize()
+        J = dsim.split_jacobian(db, out, 1)
+        tol = TOL[prec]["jac"]
+        assert np.linalg.norm(J - dref["jac"]) <= tol * np.linalg.norm(dref["jac"])
+        assert int(out["status"][1]) == 0

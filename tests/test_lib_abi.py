@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI (no GPU): the built library exports every
+function include/dsim.h declares, and the host validation and sizing calls
+behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2409_07107_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2409_07107_amd import dsim
+    if not os.path.exists(dsim.LIB_PATH):
+        pytest.fail("libdsim.so is not built (python -m paper_2409_07107_amd.build)")
+    return dsim.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dsim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(dsim_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    from paper_2409_07107_amd import dsim
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(dsim.SYMBOLS) <= set(names)
+    assert L.dsim_abi_version() == 1
+
+
+def test_default_params_validate(L):
+    from paper_2409_07107_amd import dsim
+    for prec in (dsim.F64, dsim.F32):
+        p = dsim.params(prec)
+        assert L.dsim_validate_params(ctypes.byref(p)) == 0
+    bad = [dict(dt=0.0), dict(dt=float("nan")), dict(gap_mode=2), dict(precision=5), dict(ncp_sweeps=0),
+           dict(threads=96), dict(ncp_tol=0.0), dict(rank_tol=-1.0)]
+    for b in bad:
+        p = dsim.params(dsim.F32, **b)
+        assert L.dsim_validate_params(ctypes.byref(p)) == -1, b
+
+
+def test_validate_host_accepts_workloads(L):
+    from paper_2409_07107_amd import dsim
+    for name in ("cube", "arm7", "tree36", "mixed"):
+        assert dsim.validate_host(scenes.make(name, 4, seed=1)) == (0, -1)
+
+
+@pytest.mark.parametrize("field,env,value", [("mass", 2, 0.0), ("mass", 1, -1.0), ("inertia", 3, None),
+                                             ("axis", 2, None), ("jtype", 1, None), ("parent", 2, None),
+                                             ("mu", 0, -0.1), ("cbody", 1, None)])
+def test_validate_host_rejects_nonphysical_models(L, field, env, value):
+    from paper_2409_07107_amd import dsim
+    b = scenes.make("arm7", 4, seed=1)
+    b0 = b.body_off[env]
+    c0 = b.contact_off[env]
+    if field == "mass":
+        b.mass[b0 + 3] = value
+    elif field == "inertia":
+        b.inertia[b0 + 2] = [1.0, 1.0, 5.0, 0, 0, 0]   # violates the triangle inequality
+    elif field == "axis":
+        b.axis[b0 + 1] = [1.0, 1.0, 0.0]
+    elif field == "jtype":
+        b.jtype[b0 + 2] = 1                           # free flyer below the root
+    elif field == "parent":
+        b.parent[b0 + 2] = 5                          # child listed before its parent
+    elif field == "mu":
+        b.mu[c0 + 1] = value
+    elif field == "cbody":
+        b.cbody[c0] = 9
+    rc, bad = dsim.validate_host(b)
+    assert rc in (-5, -1)
+    assert bad == env
+
+
+def test_sizes_beyond_maxima_are_rejected(L):
+    from paper_2409_07107_amd import dsim
+    b = scenes.make("arm7", 2, seed=1)
+    keep = []
+    cb = dsim._host_batch_struct(b, keep)
+    cb.max_dofs = 65
+    p = dsim.params(dsim.F32)
+    rc = L.dsim_step(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), None, 0, None)
+    assert rc == -2
+
+
+def test_empty_batch_is_a_no_op(L):
+    from paper_2409_07107_amd import dsim
+    cb = dsim.CBatch()
+    cb.n_env = 0
+    p = dsim.params(dsim.F32)
+    assert L.dsim_step(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), None, 0, None) == 0
+    assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([ctypes.c_void_p(1)] * 10), None, 0, None) == 0
+    assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), 1) == 0
+
+
+def test_null_arguments_are_rejected(L):
+    from paper_2409_07107_amd import dsim
+    b = scenes.make("arm7", 2, seed=1)
+    keep = []
+    cb = dsim._host_batch_struct(b, keep)
+    p = dsim.params(dsim.F32)
+    assert L.dsim_step(None, ctypes.byref(p), *([None] * 7), None, 0, None) == -1
+    assert L.dsim_step(ctypes.byref(cb), None, *([None] * 7), None, 0, None) == -1
+    assert L.dsim_step(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), None, 0, None) == -1
+    assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([None] * 10), None, 0, None) == -1
+
+
+def test_on_chip_sizing(L):
+    from paper_2409_07107_amd import dsim
+    b = scenes.make("tree36", 2, seed=1)
+    keep = []
+    cb = dsim._host_batch_struct(b, keep)
+    for prec in (dsim.F32, dsim.F64):
+        p = dsim.params(prec)
+        lds = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), 1)
+        assert 0 < lds <= 160 * 1024
+        assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), 1) == 0
+        assert L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), 0) < lds
