@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdsim.so")
 SOURCES = [os.path.join(HERE, "csrc", "dsim_api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", f) for f in ("dsim_core.h", "dsim_pipeline.h")] + \
+HEADERS = [os.path.join(HERE, "csrc", f) for f in ("dsim_core.h", "dsim_tree.h", "dsim_ncp.h", "dsim_pipeline.h")] + \
     [os.path.join(ROOT, "include", "dsim.h")]
 
 

@@ -175,7 +175,7 @@ void dsim_default_params(dsim_params* p, int32_t precision) {
     p->gap_mode = 0;
     p->precision = precision;
     p->ncp_sweeps = 30;
-    p->ncp_rounds = 4;
+    p->ncp_rounds = 8;
     p->newton_iters = 6;
     p->threads = 0;
     if (precision == DSIM_F32) {

@@ -1,0 +1,782 @@
+// dsim_ncp.h -- the frictional-contact NCP (Section II.B, eq. NCP) and the
+// reduced implicit system of its mode split (Section III.B-C, Appendix B).
+//
+// Solve: block Gauss-Seidel sweeps with exact per-contact solves (working
+// precision), then Newton on the equations of the realised modes (FP64) with
+// active-set changes; the natural-map residual is checked in FP64.  The
+// paper's reduced matrix A is then formed at the solution and factorised in
+// FP64 for the derivative.
+#pragma once
+
+#include "dsim_core.h"
+
+namespace dsim {
+
+// Unit slip direction t solving (s I + r Wt) t = bt for s > 0, with Wt given
+// by its eigen-decomposition (l1 >= l2 >= 0, unit eigenvector (e0, e1) of l1)
+// and bt by its coordinates beta in that basis.  |t(s)| decreases in s;
+// Newton on 1/|t(s)| = 1 (the trust-region secular equation).
+template <class R>
+DSIM_HD inline void slip_direction(R l1, R l2, R e0, R e1, R beta1, R beta2, R r, R& t0, R& t1) {
+    const R p1 = r * l1, p2 = r * (l2 > R(0) ? l2 : R(0));
+    const R tiny = R(1e-30);
+    R sv = 0;
+    if (p2 <= R(1e-12) * (p1 + tiny)) sv = fabs(beta2);
+    if (p1 + sv <= tiny) sv = fabs(beta1) + fabs(beta2);
+    for (int it = 0; it < 40; ++it) {
+        const R d1 = sv + p1, d2 = sv + p2;
+        const R q1 = beta1 / d1, q2 = d2 > tiny ? beta2 / d2 : R(0);
+        const R n2 = q1 * q1 + q2 * q2;
+        const R nrm = sqrt(n2);
+        if (!(nrm > R(0))) break;
+        const R psi = R(1) / nrm - R(1);
+        const R dn2 = q1 * q1 / d1 + (d2 > tiny ? q2 * q2 / d2 : R(0));
+        const R dpsi = dn2 / (n2 * nrm);
+        if (!(dpsi > R(0))) break;
+        R sn = sv - psi / dpsi;
+        if (sn <= R(0)) sn = R(0.5) * sv;
+        const R ds = fabs(sn - sv);
+        sv = sn;
+        if (ds <= R(4) * R(sizeof(R) == 4 ? 1.2e-7 : 2.3e-16) * (sv + p1)) break;
+    }
+    const R d1 = sv + p1, d2 = sv + p2;
+    const R q1 = d1 > tiny ? beta1 / d1 : R(0), q2 = d2 > tiny ? beta2 / d2 : R(0);
+    const R u0 = e0 * q1 - e1 * q2, u1 = e1 * q1 + e0 * q2;
+    const R nu = sqrt(u0 * u0 + u1 * u1);
+    if (nu > R(0)) {
+        t0 = u0 / nu;
+        t1 = u1 / nu;
+    } else {
+        t0 = 1;
+        t1 = 0;
+    }
+}
+
+// One-contact problem sigma = W Lam + b.  Separation if the normal free
+// velocity is non-negative, else the sticking impulse if it lies in the
+// cone, else the sliding impulse on the cone boundary.
+//
+// Sliding: sigma_N = 0 gives Lam_N = -(b_N + W_NT . Lam_T) / W_NN, so
+// sigma_T = Wt Lam_T + bt with the Schur complement Wt = W_TT - W_TN W_NT^T / W_NN
+// and bt = b_T - W_TN b_N / W_NN.  With Lam_T = -r t (|t| = 1, r = mu Lam_N)
+// and sigma_T = s t (s > 0):  (s I + r Wt) t = bt, which fixes t(r); r itself
+// solves g(r) = r (W_NN - mu W_NT . t(r)) + mu b_N = 0, with g(0) = mu b_N < 0:
+// bracketed, then refined by regula falsi (Illinois variant).
+// Sliding impulse of one contact by Newton's method from a warm start
+// (the previous sliding impulse): unknowns Lam, equations
+// Lam_T + mu Lam_N u(sigma_T) = 0 and sigma_N = 0 with sigma = W Lam + b.
+// Returns false if it does not converge to a consistent sliding impulse.
+template <class R>
+DSIM_HD inline bool slide_newton(const R* W, const R* b, R mu, R* lam) {
+    R L0 = lam[0], L1 = lam[1], L2 = lam[2];
+    const R tol = R(sizeof(R) == 4 ? 2e-6 : 1e-13);
+    for (int it = 0; it < 6; ++it) {
+        const R s0 = W[0] * L0 + W[1] * L1 + W[2] * L2 + b[0];
+        const R s1 = W[3] * L0 + W[4] * L1 + W[5] * L2 + b[1];
+        const R s2 = W[6] * L0 + W[7] * L1 + W[8] * L2 + b[2];
+        const R ns = sqrt(s0 * s0 + s1 * s1);
+        if (!(ns > R(0)) || !(L2 > R(0))) return false;
+        const R u0 = s0 / ns, u1 = s1 / ns;
+        const R f0 = L0 + mu * L2 * u0, f1 = L1 + mu * L2 * u1, f2 = s2;
+        const R lsc = mu * L2 + fabs(L0) + fabs(L1);
+        const R ssc = fabs(b[2]) + ns;
+        if (fabs(f0) <= tol * lsc && fabs(f1) <= tol * lsc && fabs(f2) <= tol * ssc) {
+            lam[0] = L0;
+            lam[1] = L1;
+            lam[2] = L2;
+            return (L0 * s0 + L1 * s1) < R(0);
+        }
+        // Jacobian rows: tangential e_a + mu u_a e_N + (mu L_N/|s_T|) (I - u u^T)_a W_T,
+        // normal W_N
+        const R c = mu * L2 / ns;
+        const R h00 = 1 - u0 * u0, h01 = -u0 * u1, h11 = 1 - u1 * u1;
+        R Jm[9];
+        for (int j = 0; j < 3; ++j) {
+            Jm[j] = c * (h00 * W[j] + h01 * W[3 + j]);
+            Jm[3 + j] = c * (h01 * W[j] + h11 * W[3 + j]);
+            Jm[6 + j] = W[6 + j];
+        }
+        Jm[0] += 1;
+        Jm[4] += 1;
+        Jm[2] += mu * u0;
+        Jm[5] += mu * u1;
+        const R c00 = Jm[4] * Jm[8] - Jm[5] * Jm[7], c01 = Jm[5] * Jm[6] - Jm[3] * Jm[8],
+                c02 = Jm[3] * Jm[7] - Jm[4] * Jm[6];
+        const R det = Jm[0] * c00 + Jm[1] * c01 + Jm[2] * c02;
+        if (!(fabs(det) > R(0))) return false;
+        const R id = R(1) / det;
+        // step = -J^-1 f (adjugate)
+        const R d0 = -(c00 * f0 + (Jm[2] * Jm[7] - Jm[1] * Jm[8]) * f1 + (Jm[1] * Jm[5] - Jm[2] * Jm[4]) * f2) * id;
+        const R d1 = -(c01 * f0 + (Jm[0] * Jm[8] - Jm[2] * Jm[6]) * f1 + (Jm[2] * Jm[3] - Jm[0] * Jm[5]) * f2) * id;
+        const R d2 = -(c02 * f0 + (Jm[1] * Jm[6] - Jm[0] * Jm[7]) * f1 + (Jm[0] * Jm[4] - Jm[1] * Jm[3]) * f2) * id;
+        L0 += d0;
+        L1 += d1;
+        L2 += d2;
+    }
+    return false;
+}
+
+template <class R>
+DSIM_HD inline int local_solve(const R* W, const R* Wi, const R* b, R mu, R* lam, int prev_mode) {
+    if (b[2] >= R(0)) {
+        lam[0] = lam[1] = lam[2] = 0;
+        return BRK;
+    }
+    R s[3];
+    mat3vec(Wi, b, s);
+    s[0] = -s[0]; s[1] = -s[1]; s[2] = -s[2];
+    const R nt = sqrt(s[0] * s[0] + s[1] * s[1]);
+    if (s[2] > R(0) && nt <= mu * s[2]) {
+        lam[0] = s[0]; lam[1] = s[1]; lam[2] = s[2];
+        return STK;
+    }
+    if (prev_mode == SLD && mu > R(0) && slide_newton(W, b, mu, lam)) return SLD;
+    const R wnn = W[8];
+    if (mu <= R(0) || !(wnn > R(0))) {
+        lam[0] = 0;
+        lam[1] = 0;
+        lam[2] = wnn > R(0) ? -b[2] / wnn : R(0);
+        return SLD;
+    }
+    const R w00 = W[0] - W[2] * W[6] / wnn;
+    const R w11 = W[4] - W[5] * W[7] / wnn;
+    const R w01 = R(0.5) * ((W[1] - W[2] * W[7] / wnn) + (W[3] - W[5] * W[6] / wnn));
+    const R bt0 = b[0] - W[2] * b[2] / wnn, bt1 = b[1] - W[5] * b[2] / wnn;
+    // eigen-decomposition of the symmetric 2x2 Wt; (e0, e1) is the larger of
+    // (l1 - w11, w01) and (w01, l1 - w00), both solutions of (Wt - l1 I) e = 0
+    const R disc = sqrt(R(0.25) * (w00 - w11) * (w00 - w11) + w01 * w01);
+    const R l1 = R(0.5) * (w00 + w11) + disc, l2 = R(0.5) * (w00 + w11) - disc;
+    R e0 = l1 - w11, e1 = w01;
+    {
+        const R f0 = w01, f1 = l1 - w00;
+        if (f0 * f0 + f1 * f1 > e0 * e0 + e1 * e1) {
+            e0 = f0;
+            e1 = f1;
+        }
+        const R nn = sqrt(e0 * e0 + e1 * e1);
+        if (nn > R(0)) {
+            e0 /= nn;
+            e1 /= nn;
+        } else {
+            e0 = 1;
+            e1 = 0;
+        }
+    }
+    const R beta1 = e0 * bt0 + e1 * bt1, beta2 = -e1 * bt0 + e0 * bt1;
+    R t0 = 1, t1 = 0;
+    auto gfun = [&](R r) -> R {
+        slip_direction(l1, l2, e0, e1, beta1, beta2, r, t0, t1);
+        return r * (wnn - mu * (W[6] * t0 + W[7] * t1)) + mu * b[2];
+    };
+    R rlo = 0, glo = mu * b[2];
+    R rhi = -mu * b[2] / wnn, ghi = gfun(rhi);
+    for (int it = 0; it < 60 && !(ghi > R(0)); ++it) {
+        rlo = rhi;
+        glo = ghi;
+        rhi *= R(2);
+        ghi = gfun(rhi);
+    }
+    R r = rhi;
+    if (ghi > R(0)) {
+        int side = 0;
+        const R rtol = R(sizeof(R) == 4 ? 1e-7 : 1e-15);
+        for (int it = 0; it < 100; ++it) {
+            r = (rlo * ghi - rhi * glo) / (ghi - glo);
+            if (!(r > rlo && r < rhi)) r = R(0.5) * (rlo + rhi);
+            const R gr = gfun(r);
+            if (gr > R(0)) {
+                rhi = r;
+                ghi = gr;
+                if (side == 1) glo *= R(0.5);
+                side = 1;
+            } else {
+                rlo = r;
+                glo = gr;
+                if (side == -1) ghi *= R(0.5);
+                side = -1;
+            }
+            if (rhi - rlo <= rtol * rhi || gr == R(0)) break;
+        }
+    }
+    gfun(r);
+    lam[0] = -r * t0;
+    lam[1] = -r * t1;
+    lam[2] = r / mu;
+    return SLD;
+}
+
+// `sweeps` block Gauss-Seidel sweeps, run by wavefront 0: sigma = G Lam + g
+// is kept up to date in LDS; each contact update is computed redundantly by
+// all lanes, then the lanes update sigma row-parallel.
+template <class R>
+DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
+    const int k = E.k, nc = E.nc;
+    if (T.wave == 0) {
+        for (int s = 0; s < sweeps; ++s) {
+            for (int c = 0; c < nc; ++c) {
+                const int o = 3 * c;
+                R W[9];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) W[3 * i + j] = E.G[(o + i) * k + o + j];
+                const R L[3] = {E.Lam[o], E.Lam[o + 1], E.Lam[o + 2]};
+                R b[3];
+                for (int i = 0; i < 3; ++i)
+                    b[i] = E.sig[o + i] - (W[3 * i] * L[0] + W[3 * i + 1] * L[1] + W[3 * i + 2] * L[2]);
+                R Ln[3] = {L[0], L[1], L[2]};
+                const int md = local_solve(W, E.Winv + 9 * c, b, E.mu[c], Ln, E.lmode[c]);
+                const R d0 = Ln[0] - L[0], d1 = Ln[1] - L[1], d2 = Ln[2] - L[2];
+                T.wave_sync();
+                for (int r = T.lane; r < k; r += T.wsize)
+                    E.sig[r] += E.G[r * k + o] * d0 + E.G[r * k + o + 1] * d1 + E.G[r * k + o + 2] * d2;
+                if (T.lane == 0) {
+                    E.Lam[o] = Ln[0];
+                    E.Lam[o + 1] = Ln[1];
+                    E.Lam[o + 2] = Ln[2];
+                    E.lmode[c] = md;
+                }
+                T.wave_sync();
+            }
+        }
+    }
+    T.sync();
+}
+
+template <class R>
+DSIM_HD void update_sigma(const Team& T, Env<R>& E) {
+    const int k = E.k;
+    for (int r = T.tid; r < k; r += T.nt) {
+        R s = E.g[r];
+        for (int c = 0; c < k; ++c) s += E.G[r * k + c] * E.Lam[c];
+        E.sig[r] = s;
+    }
+    T.sync();
+}
+
+// sigma = Gd Ld + gd in FP64.
+template <class R>
+DSIM_HD void fp64_sigma(const Team& T, Env<R>& E) {
+    const int k = E.k;
+    for (int r = T.tid; r < k; r += T.nt) {
+        double s = E.gd[r];
+        for (int c = 0; c < k; ++c) s += E.Gd[r * k + c] * E.Ld[c];
+        E.dsig[r] = s;
+    }
+    T.sync();
+}
+
+// Scales of the residuals: free velocity (with the gravity step) and impulse.
+template <class R>
+DSIM_HD inline void scales(const Env<R>& E, const Params& P, double& smax, double& lmax) {
+    smax = 1e-300;
+    lmax = 1e-300;
+    for (int r = 0; r < E.k; ++r) {
+        const double a = fabs(E.gd[r]);
+        smax = a > smax ? a : smax;
+        const double l = fabs(E.Ld[r]);
+        lmax = l > lmax ? l : lmax;
+    }
+    const double sg = P.dt * (fabs(P.gx) + fabs(P.gy) + fabs(P.gz));
+    smax = smax > sg ? smax : sg;
+}
+
+// Reduced variables of the mode set in cmode (Section III.C, Appendix B):
+// sticking contacts first (3 each), then sliding contacts (2 each, in the
+// tangent plane of the cone, R = [Lam/|Lam|, e_z x sigma_T/|sigma_T|]).  Row
+// vectors select the equation rows; the sliding rows are scaled so that the
+// coefficients stay bounded: the first by 1/cos(phi) (row e_z), the second by
+// alpha/(1 + alpha) (row w u_perp, diagonal 1 - w, w = mu Lam_N / (mu Lam_N +
+// |sigma_T|)).  Uses Ld and dsig.
+template <class R>
+DSIM_HD void reduced_vars(const Team& T, Env<R>& E) {
+    if (T.tid == 0) {
+        int m = 0, nstk = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int c = 0; c < E.nc; ++c) {
+                const int md = E.cmode[c];
+                if (pass == 0 && md == STK) {
+                    for (int a = 0; a < 3; ++a) {
+                        E.vctc[m] = c;
+                        E.vcmp[m] = a;
+                        for (int i = 0; i < 3; ++i) {
+                            E.vrow[3 * m + i] = (i == a) ? 1.0 : 0.0;
+                            E.vcol[3 * m + i] = (i == a) ? 1.0 : 0.0;
+                        }
+                        E.vdiag[m] = 0;
+                        ++m;
+                    }
+                    ++nstk;
+                } else if (pass == 1 && md == SLD) {
+                    const int o = 3 * c;
+                    const double s0 = E.dsig[o], s1 = E.dsig[o + 1];
+                    const double ns = sqrt(s0 * s0 + s1 * s1);
+                    const double u0 = ns > 0 ? s0 / ns : 1.0, u1 = ns > 0 ? s1 / ns : 0.0;
+                    const double L0 = E.Ld[o], L1 = E.Ld[o + 1], L2 = E.Ld[o + 2];
+                    const double nl = sqrt(L0 * L0 + L1 * L1 + L2 * L2);
+                    const double mln = double(E.mu[c]) * L2;
+                    const double w = (mln + ns) > 0 ? mln / (mln + ns) : 1.0;
+                    // along r1 = Lam/|Lam|: row e_z
+                    E.vctc[m] = c;
+                    E.vcmp[m] = 0;
+                    E.vrow[3 * m] = 0;
+                    E.vrow[3 * m + 1] = 0;
+                    E.vrow[3 * m + 2] = 1;
+                    E.vcol[3 * m] = L0 / nl;
+                    E.vcol[3 * m + 1] = L1 / nl;
+                    E.vcol[3 * m + 2] = L2 / nl;
+                    E.vdiag[m] = 0;
+                    ++m;
+                    // along r2 = e_z x u: row w u_perp, diagonal 1 - w
+                    E.vctc[m] = c;
+                    E.vcmp[m] = 1;
+                    E.vrow[3 * m] = -w * u1;
+                    E.vrow[3 * m + 1] = w * u0;
+                    E.vrow[3 * m + 2] = 0;
+                    E.vcol[3 * m] = -u1;
+                    E.vcol[3 * m + 1] = u0;
+                    E.vcol[3 * m + 2] = 0;
+                    E.vdiag[m] = 1 - w;
+                    ++m;
+                }
+            }
+        E.hdr[1] = m;
+        E.hdr[2] = nstk;
+    }
+    T.sync();
+}
+
+// A = rows^T G cols + diag (FP64), m x m row-major.
+template <class R>
+DSIM_HD void build_A(const Team& T, Env<R>& E) {
+    const int m = E.hdr[1], k = E.k;
+    for (int idx = T.tid; idx < m * m; idx += T.nt) {
+        const int i = idx / m, j = idx - i * m;
+        const int ci = 3 * E.vctc[i], cj = 3 * E.vctc[j];
+        const double* ri = E.vrow + 3 * i;
+        const double* cv = E.vcol + 3 * j;
+        double s = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (ri[a] == 0.0) continue;
+            double t = 0;
+            for (int b = 0; b < 3; ++b) t += E.Gd[(ci + a) * k + cj + b] * cv[b];
+            s += ri[a] * t;
+        }
+        if (i == j) s += E.vdiag[i];
+        E.A[idx] = s;
+    }
+    T.sync();
+}
+
+// In-place elimination of A with pivoting.  Sticking variables come first
+// and are eliminated with symmetric (diagonal) pivoting: that block is G_SS,
+// symmetric positive semidefinite, so this is a pivoted LDL^T (square-root
+// free Cholesky) of it.  Once it is exhausted the elimination continues with
+// complete pivoting (the sliding block's Schur complement; the remaining
+// sticking rows and columns are zero).  Pivots below rank_tol times the
+// largest entry of A end the elimination; the solves then set the remaining
+// variables to zero (basic solution).  Leaves L (unit, below the diagonal)
+// and U in A, the row and column permutations in rperm/cperm, the rank in
+// hdr[4].
+template <class R>
+DSIM_HD void factor_A(const Team& T, Env<R>& E, double rank_tol) {
+    const int m = E.hdr[1];
+    const int nst = 3 * E.hdr[2];
+    double* A = E.A;
+    if (T.tid == 0) {
+        for (int i = 0; i < m; ++i) {
+            E.rperm[i] = i;
+            E.cperm[i] = i;
+        }
+        E.hdr[4] = m;
+    }
+    T.sync();
+    double scale = 0;
+    for (int i = 0; i < m * m; ++i) {
+        const double a = fabs(A[i]);
+        scale = a > scale ? a : scale;
+    }
+    const double tol = rank_tol * (scale > 0 ? scale : 1.0);
+    int rank = 0;
+    bool stick_phase = nst > 0;
+    for (int p = 0; p < m; ++p) {
+        // pivot choice (every thread computes the same, reading A)
+        int pr = -1, pc = -1;
+        double best = -1;
+        if (stick_phase && p < nst) {
+            for (int i = p; i < nst; ++i) {
+                const double a = fabs(A[i * m + i]);
+                if (a > best) {
+                    best = a;
+                    pr = i;
+                    pc = i;
+                }
+            }
+            if (best <= tol) stick_phase = false;
+        }
+        if (!(stick_phase && p < nst)) {
+            best = -1;
+            for (int i = p; i < m; ++i)
+                for (int j = p; j < m; ++j) {
+                    const double a = fabs(A[i * m + j]);
+                    if (a > best) {
+                        best = a;
+                        pr = i;
+                        pc = j;
+                    }
+                }
+        }
+        if (best <= tol || pr < 0) break;
+        T.sync();
+        if (pr != p)
+            for (int j = T.tid; j < m; j += T.nt) {
+                const double t = A[p * m + j];
+                A[p * m + j] = A[pr * m + j];
+                A[pr * m + j] = t;
+            }
+        T.sync();
+        if (pc != p)
+            for (int i = T.tid; i < m; i += T.nt) {
+                const double t = A[i * m + p];
+                A[i * m + p] = A[i * m + pc];
+                A[i * m + pc] = t;
+            }
+        if (T.tid == 0) {
+            int t = E.rperm[p];
+            E.rperm[p] = E.rperm[pr];
+            E.rperm[pr] = t;
+            t = E.cperm[p];
+            E.cperm[p] = E.cperm[pc];
+            E.cperm[pc] = t;
+        }
+        T.sync();
+        const double piv = A[p * m + p];
+        for (int i = p + 1 + T.tid; i < m; i += T.nt) A[i * m + p] /= piv;
+        T.sync();
+        const int rem = m - p - 1;
+        for (int idx = T.tid; idx < rem * rem; idx += T.nt) {
+            const int i = p + 1 + idx / rem, j = p + 1 + idx % rem;
+            A[i * m + j] -= A[i * m + p] * A[p * m + j];
+        }
+        T.sync();
+        rank = p + 1;
+    }
+    if (T.tid == 0) E.hdr[4] = rank;
+    T.sync();
+}
+
+// Solve A x = b with the factors for one right-hand side (basic solution):
+// b permuted by rperm, free variables zero, result scattered by cperm.
+DSIM_HD inline void lu_solve(const double* A, int m, int rank, const int* rperm, const int* cperm,
+                             const double* b, double* y, double* x) {
+    for (int i = 0; i < m; ++i) y[i] = b[rperm[i]];
+    for (int i = 0; i < rank; ++i) {
+        double s = y[i];
+        for (int j = 0; j < i; ++j) s -= A[i * m + j] * y[j];
+        y[i] = s;
+    }
+    for (int i = rank; i < m; ++i) y[i] = 0;
+    for (int i = rank - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int j = i + 1; j < rank; ++j) s -= A[i * m + j] * y[j];
+        y[i] = s / A[i * m + i];
+    }
+    for (int i = 0; i < m; ++i) x[cperm[i]] = y[i];
+}
+
+// Newton system of the mode equations (Section III.B) in the impulses of the
+// active contacts (3 unknowns each, sticking contacts first): sticking
+// sigma_c = 0; sliding Lam_T + mu Lam_N u = 0 (u = sigma_T/|sigma_T|) and
+// sigma_N = 0.  Fills A (its exact Jacobian), rhs = -F and the unknowns'
+// contact and component; dsc[1] gets the scaled residual max |F_i| / scale
+// and dsc[3] its squared 2-norm (velocity rows scaled by the free-velocity
+// scale, impulse rows by the impulse scale).  Uses Ld and dsig.
+template <class R>
+DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
+    const int k = E.k;
+    if (T.tid == 0) {
+        int m = 0, nstk = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int c = 0; c < E.nc; ++c) {
+                const int md = E.cmode[c];
+                if ((pass == 0 && md == STK) || (pass == 1 && md == SLD)) {
+                    for (int a = 0; a < 3; ++a) {
+                        E.vctc[m] = c;
+                        E.vcmp[m] = a;
+                        ++m;
+                    }
+                    if (md == STK) ++nstk;
+                }
+                if (pass == 1 && md == SLD) {
+                    const double s0 = E.dsig[3 * c], s1 = E.dsig[3 * c + 1];
+                    double ns = sqrt(s0 * s0 + s1 * s1);
+                    double u0, u1;
+                    if (ns > 1e-300) {
+                        u0 = s0 / ns;
+                        u1 = s1 / ns;
+                    } else {
+                        // no slip yet: hold the friction direction
+                        const double l0 = E.Ld[3 * c], l1 = E.Ld[3 * c + 1];
+                        const double nl = sqrt(l0 * l0 + l1 * l1);
+                        u0 = nl > 0 ? -l0 / nl : 1.0;
+                        u1 = nl > 0 ? -l1 / nl : 0.0;
+                        ns = 1e-300;
+                    }
+                    double* f = E.dfr + 4 * c;
+                    f[0] = u0;
+                    f[1] = u1;
+                    f[2] = double(E.mu[c]) * E.Ld[3 * c + 2] / ns;  // mu Lam_N / |sigma_T|
+                }
+            }
+        E.hdr[1] = m;
+        E.hdr[2] = nstk;
+    }
+    T.sync();
+    const int m = E.hdr[1];
+    for (int idx = T.tid; idx < m * m; idx += T.nt) {
+        const int i = idx / m, j = idx - i * m;
+        const int ci = E.vctc[i], ai = E.vcmp[i];
+        const int cj = E.vctc[j], aj = E.vcmp[j];
+        const int col = 3 * cj + aj;
+        double v;
+        if (E.cmode[ci] == SLD && ai < 2) {
+            const double* f = E.dfr + 4 * ci;
+            const double u0 = f[0], u1 = f[1], coef = f[2];
+            const double h0 = (ai == 0) ? 1.0 - u0 * u0 : -u0 * u1;
+            const double h1 = (ai == 0) ? -u0 * u1 : 1.0 - u1 * u1;
+            v = coef * (h0 * E.Gd[(3 * ci) * k + col] + h1 * E.Gd[(3 * ci + 1) * k + col]);
+            if (cj == ci && aj == ai) v += 1.0;
+            if (cj == ci && aj == 2) v += double(E.mu[ci]) * (ai == 0 ? u0 : u1);
+        } else {
+            v = E.Gd[(3 * ci + ai) * k + col];
+        }
+        E.A[idx] = v;
+    }
+    if (T.tid == 0) {
+        double smax, lmax;
+        scales(E, P, smax, lmax);
+        double res = 0, nrm = 0;
+        for (int i = 0; i < m; ++i) {
+            const int c = E.vctc[i], a = E.vcmp[i];
+            double f, rel;
+            if (E.cmode[c] == SLD && a < 2) {
+                const double* fr = E.dfr + 4 * c;
+                f = E.Ld[3 * c + a] + double(E.mu[c]) * E.Ld[3 * c + 2] * fr[a];
+                rel = fabs(f) / lmax;
+            } else {
+                f = E.dsig[3 * c + a];
+                rel = fabs(f) / smax;
+            }
+            E.rhs[i] = -f;
+            res = rel > res ? rel : res;
+            nrm += rel * rel;
+        }
+        E.dsc[1] = res;
+        E.dsc[3] = nrm;
+    }
+    T.sync();
+}
+
+// Newton refinement of the NCP solution (on Ld, FP64) with a fixed mode set,
+// with active-set changes and backtracking.  When the equations are solved
+// but an inequality of the mode set is violated, the offending contacts
+// change mode (penetrating breaking contact -> sticking, negative normal
+// impulse -> breaking, sticking impulse outside the cone -> sliding, slip not
+// opposed by friction -> sticking) and the iteration continues; a step that
+// increases the residual of the same mode set is halved.  Returns true on a
+// consistent solution.
+template <class R>
+DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
+    const int k = E.k, nc = E.nc;
+    const int max_changes = 2 * nc + 2;
+    int changes = 0, since = 0;
+    bool ok = false;
+    if (T.tid == 0) {
+        E.hdr[12] = 0;
+        E.dsc[0] = 1e300;
+    }
+    T.sync();
+    // bounded work: at most 8 (newton_iters + 1) evaluations per refinement
+    for (int guard = 0; guard < 8 * (P.newton_iters + 1); ++guard) {
+        fp64_sigma(T, E);
+        newton_system(T, E, P);
+        const int m = E.hdr[1];
+        if (T.tid == 0) {
+            const double res = E.dsc[1], nrm = E.dsc[3];
+            const int conv = (res <= P.ncp_tol) ? 1 : 0;
+            int back = 0;
+            if (!conv && since > 0 && nrm > E.dsc[0] && E.hdr[12] < 12) {
+                back = 1;
+                E.hdr[12] += 1;
+                for (int r = 0; r < k; ++r) E.Ld[r] = 0.5 * (E.Ld1[r] + E.Ld[r]);
+            } else {
+                E.hdr[12] = 0;
+                E.dsc[0] = nrm;
+                for (int r = 0; r < k; ++r) E.Ld1[r] = E.Ld[r];
+            }
+#ifdef DSIM_DEBUG_PRINT
+            printf("refine env %d it %d res %.3e back %d m %d modes", E.e, guard, res, back, m);
+            for (int c = 0; c < nc; ++c) printf(" %d", E.cmode[c]);
+            printf("\n");
+#endif
+            int viol = 0;
+            // mode inequalities are checked at a solution of the mode
+            // equations, or when Newton stalls on the current mode set
+            if (conv || (!back && since >= P.newton_iters)) {
+                double smax, lmax;
+                scales(E, P, smax, lmax);
+                const double tl = 1e2 * P.ncp_tol;
+                for (int c = 0; c < nc; ++c) {
+                    const double L0 = E.Ld[3 * c], L1 = E.Ld[3 * c + 1], L2 = E.Ld[3 * c + 2];
+                    const double S0 = E.dsig[3 * c], S1 = E.dsig[3 * c + 1], S2 = E.dsig[3 * c + 2];
+                    const double mu = E.mu[c];
+                    int md = E.cmode[c];
+                    if (md == BRK) {
+                        if (S2 < -tl * smax) md = STK;
+                    } else if (L2 < -tl * lmax) {
+                        md = BRK;
+                    } else if (md == STK) {
+                        if (sqrt(L0 * L0 + L1 * L1) > mu * L2 + tl * lmax) md = SLD;
+                    } else if (L0 * S0 + L1 * S1 > 0) {
+                        md = STK;
+                    }
+                    if (md != E.cmode[c]) {
+                        ++viol;
+                        E.cmode[c] = md;
+                        if (md == BRK) E.Ld[3 * c] = E.Ld[3 * c + 1] = E.Ld[3 * c + 2] = 0;
+                    }
+                }
+                if (viol) {
+                    E.hdr[12] = 0;
+                    E.dsc[0] = 1e300;
+                }
+            }
+            E.hdr[9] = conv;
+            E.hdr[11] = viol;
+            E.hdr[13] = back;
+        }
+        T.sync();
+        const int conv = E.hdr[9], viol = E.hdr[11];
+        if (E.hdr[13]) continue;  // re-evaluate at the shortened step
+        if (conv && !viol) {
+            ok = true;
+            break;
+        }
+        if (viol) {
+            if (++changes > max_changes) break;
+            since = 0;
+            continue;
+        }
+        if (since >= P.newton_iters) break;
+        ++since;
+        factor_A(T, E, P.rank_tol);
+        if (T.tid == 0) lu_solve(E.A, m, E.hdr[4], E.rperm, E.cperm, E.rhs, E.ytmp, E.X);
+        T.sync();
+        for (int i = T.tid; i < m; i += T.nt) E.Ld[3 * E.vctc[i] + E.vcmp[i]] += E.X[i];
+        T.sync();
+    }
+    if (T.tid == 0) E.hdr[6] = ok ? 1 : 0;
+    T.sync();
+    return ok;
+}
+
+// The NCP: sweeps in working precision, refinement in FP64, repeated in
+// rounds until the refinement reaches a consistent solution; then the
+// paper's reduced system at the solution, factorised for the derivative.
+template <class R>
+DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P) {
+    const int k = E.k;
+    for (int r = T.tid; r < k; r += T.nt) {
+        E.Lam[r] = 0;
+        E.sig[r] = E.g[r];
+    }
+    for (int c = T.tid; c < E.nc; c += T.nt) E.lmode[c] = BRK;
+    T.sync();
+    bool ok = false;
+    for (int round = 0; round < P.ncp_rounds && k > 0; ++round) {
+        nsgs(T, E, P.ncp_sweeps);
+        for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = double(E.Lam[r]);
+        for (int c = T.tid; c < E.nc; c += T.nt) E.cmode[c] = E.lmode[c];
+        T.sync();
+        ok = polish(T, E, P);
+        if (ok) break;
+    }
+    if (!ok && k > 0) {
+        // keep the Gauss-Seidel iterate and its modes
+        for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = double(E.Lam[r]);
+        for (int c = T.tid; c < E.nc; c += T.nt) E.cmode[c] = E.lmode[c];
+        T.sync();
+    }
+    for (int r = T.tid; r < k; r += T.nt) E.Lam[r] = R(E.Ld[r]);
+    T.sync();
+    if (k > 0) {
+        fp64_sigma(T, E);
+        reduced_vars(T, E);
+        build_A(T, E);
+        factor_A(T, E, P.rank_tol);
+    }
+    if (T.tid == 0) {
+        E.hdr[5] = (ok || k == 0) ? 0 : ST_POLISH;
+        if (k == 0) {
+            E.hdr[1] = 0;
+            E.hdr[4] = 0;
+        }
+    }
+    T.sync();
+}
+
+// FP64 natural-map residual (Section II.B) |Lam - P_K(Lam - rho (sigma +
+// Gamma(sigma)))| with rho = 3 / trace(G_ii), relative to the impulse scale;
+// mode margins; sets the status bits.
+template <class R>
+DSIM_HD void residual_and_flags(const Team& T, Env<R>& E, const Params& P) {
+    if (T.tid == 0) {
+        const int k = E.k;
+        double smax, lmax;
+        scales(E, P, smax, lmax);
+        double res = 0;
+        bool degen = false;
+        for (int c = 0; c < E.nc; ++c) {
+            double s[3], L[3];
+            for (int a = 0; a < 3; ++a) {
+                s[a] = E.dsig[3 * c + a];
+                L[a] = E.Ld[3 * c + a];
+            }
+            const double mu = double(E.mu[c]);
+            const double tr = E.Gd[(3 * c) * k + 3 * c] + E.Gd[(3 * c + 1) * k + 3 * c + 1] +
+                              E.Gd[(3 * c + 2) * k + 3 * c + 2];
+            const double rho = tr > 0 ? 3.0 / tr : 1.0;
+            const double st = sqrt(s[0] * s[0] + s[1] * s[1]);
+            const double y[3] = {L[0] - rho * s[0], L[1] - rho * s[1], L[2] - rho * (s[2] + mu * st)};
+            const double yt = sqrt(y[0] * y[0] + y[1] * y[1]);
+            double p[3];
+            if (yt <= mu * y[2]) {
+                p[0] = y[0];
+                p[1] = y[1];
+                p[2] = y[2];
+            } else if (mu * yt <= -y[2]) {
+                p[0] = p[1] = p[2] = 0;
+            } else {
+                const double beta = (mu * yt + y[2]) / (mu * mu + 1.0);
+                p[0] = mu * beta * y[0] / yt;
+                p[1] = mu * beta * y[1] / yt;
+                p[2] = beta;
+            }
+            const double r = sqrt((L[0] - p[0]) * (L[0] - p[0]) + (L[1] - p[1]) * (L[1] - p[1]) +
+                                  (L[2] - p[2]) * (L[2] - p[2]));
+            res = r > res ? r : res;
+            const double eps = P.mode_eps;
+            const double lt = sqrt(L[0] * L[0] + L[1] * L[1]);
+            const int md = E.cmode[c];
+            if (md == BRK) degen = degen || (s[2] <= eps * smax);
+            if (md == STK) degen = degen || (L[2] <= eps * lmax) || (mu * L[2] - lt <= eps * lmax);
+            if (md == SLD) degen = degen || (L[2] <= eps * lmax) || (st <= eps * smax);
+        }
+        int st = E.hdr[5];
+        if (k > 0 && res > P.ncp_tol * lmax) st |= ST_NCP;
+        if (E.hdr[4] < E.hdr[1]) st |= ST_RANK;
+        if (degen) st |= ST_DEGEN;
+        E.hdr[5] = st;
+    }
+    T.sync();
+}
+
+}  // namespace dsim

@@ -6,7 +6,8 @@ nothing here comes from the HIP path.
 
 Each file holds, per listed environment: index, v+ (n_v), J^T Lam (n_v),
 modes (n_c), margin, solver ok flag, uniqueness of the v+ derivative, and the
-full Jacobian d v+ / d(dq, v, tau) (n_v x 3 n_v).
+full Jacobian d v+ / d(dq, v, tau) (n_v x 3 n_v), and the NCP data (G, g,
+mu) so that a different but valid GPU solution can be recognised.
 """
 from __future__ import annotations
 
@@ -41,6 +42,7 @@ def _one(e):
     r = step.forward(env)
     d = derivative.ift(env, r)
     return dict(env=e, vnext=r["vnext"], JtLam=r["JtLam"], modes=np.array(r["modes"], dtype=np.int8),
+                G=r["G"], g=r["g"], mu=r["model"].mu,
                 margin=r["margin"], ok=bool(r["info"]["ok"]), unique=bool(d["unique_v"]), jac=d["jac"],
                 residual=float(r["residual"].max()) if len(r["residual"]) else 0.0)
 
@@ -52,7 +54,7 @@ def make(name):
     with Pool(min(8, len(envs))) as p:
         res = p.map(_one, envs)
     out = dict(envs=np.array(envs), workload=wl, n_env=n, seed=seed)
-    for key in ("vnext", "JtLam", "modes", "jac"):
+    for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu"):
         out[key] = np.array([r[key] for r in res], dtype=object if wl == "mixed" else None)
     for key in ("margin", "ok", "unique", "residual"):
         out[key] = np.array([r[key] for r in res])
