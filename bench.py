@@ -25,8 +25,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak
+# ALU peak of the path: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+# = 78.6 TFLOP/s.  The kernels are built without packed FP32 instructions, so
+# FP32 and FP64 vector arithmetic both issue at this rate (the 157.3 TFLOP/s
+# FP32 figure assumes packed dual FP32).
+PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 WORKLOAD = dict(name="tree36", n_env=16384, seed=0)
+KERNEL = "env_kernel<float, jacobian>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "env_kernel_f32_jacobian_tree36_16384_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the timed kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel
+    calibration), or None when absent or taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    from paper_2409_07107_amd.profiling import source_digest
+    if t.get("source_sha1") != source_digest():
+        return None
+    return float(t["bytes_per_launch"])
 
 
 def algorithmic_flops(batch, modes, sweeps):
@@ -70,31 +90,35 @@ def algorithmic_flops(batch, modes, sweeps):
     return f32, f64
 
 
-def _oracle_one(args):
-    name, n_env, seed, e = args
-    from paper_2409_07107_amd import scenes
+def _oracle_init():
+    import torch
+    from threadpoolctl import threadpool_limits
+    torch.set_num_threads(1)
+    threadpool_limits(1)
+
+
+def _oracle_one(env):
     from oracle import derivative, step
-    batch = scenes.make(name, n_env, seed=seed)
-    env = batch.env(e)
     r = step.forward(env)
     derivative.ift(env, r)
-    return e
+    return 1
 
 
-def cpu_baseline(name, n_env, seed, cores):
+def cpu_baseline(batch, cores, per_core=2):
     """The FP64 oracle (step + implicit-function-theorem Jacobian), timed on
-    the host cores on a bounded sample of the same workload."""
-    from multiprocessing import Pool
-    n_sample = 2 * cores
-    envs = list(np.linspace(0, n_env - 1, n_sample).astype(int))
-    with Pool(cores) as pool:
-        pool.map(_oracle_one, [(name, 8, seed, 0)] * cores)  # warm the workers (imports)
+    the host cores on a bounded sample of the same workload: per_core
+    environments per worker process, evenly spaced over the batch."""
+    from multiprocessing import get_context
+    n_sample = per_core * cores
+    envs = [batch.env(int(e)) for e in np.linspace(0, batch.n_env - 1, n_sample).astype(int)]
+    with get_context("fork").Pool(cores, initializer=_oracle_init) as pool:
+        pool.map(_oracle_one, envs[:cores], chunksize=1)  # warm the workers (imports, first calls)
         t0 = time.perf_counter()
-        pool.map(_oracle_one, [(name, n_env, seed, int(e)) for e in envs])
+        pool.map(_oracle_one, envs, chunksize=1)
         dt = time.perf_counter() - t0
     return dict(value=n_sample / dt, unit="evals/s", cores=cores, kind="oracle",
-                sample=f"{n_sample} envs of the same {n_env}-env batch (evenly spaced), each the full "
-                       f"FP64 oracle step + Jacobian, {cores} worker processes, {dt:.1f} s wall")
+                sample=f"{n_sample} of the {batch.n_env} environments (evenly spaced), each the full FP64 "
+                       f"oracle step + Jacobian, {cores} single-threaded worker processes, {dt:.1f} s wall")
 
 
 def run(args):
@@ -104,7 +128,8 @@ def run(args):
         raise SystemExit("bench.py needs a GPU")
     batch = scenes.make(WORKLOAD["name"], WORKLOAD["n_env"], seed=WORKLOAD["seed"])
     results = {}
-    for prec, steps in ((dsim.F32, args.steps), (dsim.F64, max(3, args.steps // 4))):
+    runs = [(dsim.F32, args.steps)] + ([] if args.only_f32 else [(dsim.F64, max(3, args.steps // 4))])
+    for prec, steps in runs:
         db = dsim.DeviceBatch(batch, precision=prec)
         p = db.params()
         out = dsim.step_jacobian(db, p=p)
@@ -129,14 +154,17 @@ def run(args):
                              lds=db.lds_bytes(p, dsim.ENTRY_JACOBIAN), sweeps=p.ncp_sweeps)
         print(f"[bench] precision {prec}: {steps} steps, {wall / steps * 1e3:.3f} ms/step, "
               f"kernel {kern_ms:.3f} ms, flagged {int(((status & 17) != 0).sum())}", file=sys.stderr, flush=True)
+    if args.only_f32:
+        return
     r32, r64 = results[dsim.F32], results[dsim.F64]
     n = batch.n_env
     value = n * r32["steps"] / r32["wall"]
     fp64_value = n * r64["steps"] / r64["wall"]
     f32, f64 = algorithmic_flops(batch, r32["modes"], r32["sweeps"])
     achieved = (f32 + f64) / (r32["kern_ms"] * 1e-3) / 1e12
+    traffic = measured_traffic()
     cores = int(os.environ.get("BENCH_CPU_CORES", min(16, os.cpu_count() or 1)))
-    cpu = None if args.no_cpu else cpu_baseline(WORKLOAD["name"], n, WORKLOAD["seed"], cores)
+    cpu = None if args.no_cpu else cpu_baseline(batch, cores)
     line = {
         "metric": "step-derivative evals/sec (36-dof, 8 contacts), FP32-batched vs FP64 plain",
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": r32["steps"], "warmup": args.warmup,
@@ -148,9 +176,9 @@ def run(args):
                    "n_env": n, "seed": WORKLOAD["seed"], "entry": "dsim_step_jacobian"},
         "fp64_plain": {"value": fp64_value, "unit": "evals/s", "steps": r64["steps"],
                        "ms_per_step": r64["wall"] / r64["steps"] * 1e3, "fp32_over_fp64": value / fp64_value},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "kernel": "env_kernel<float, jacobian>", "kernel_ms": r32["kern_ms"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
+                     "kernel": KERNEL, "kernel_ms": r32["kern_ms"],
                      "algorithmic_flops_per_launch": f32 + f64, "fp64_flops_per_launch": f64,
                      "lds_bytes_per_team": r32["lds"]},
         "cpu_baseline": cpu,
@@ -160,17 +188,37 @@ def run(args):
     print(json.dumps(line), flush=True)
 
 
+def copy_probe(nbytes):
+    """One plain elementwise copy kernel (dst = src * 1 in FP32) over nbytes:
+    the reference reading of the HBM byte counters (FETCH_SIZE, WRITE_SIZE)
+    for a kernel that reads nbytes and writes nbytes."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only-f32", action="store_true",
+                    help="time only the FP32 launch and print no JSON line (for profiler runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="run one plain copy of BYTES and exit (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: environments are independent and a multi-GPU run would "
-              "shard the batch with no communication (see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("this benchmark runs on one GPU only: environments are independent, so a multi-GPU run "
+              "would shard the batch with no communication; use --gpus 1", file=sys.stderr)
         raise SystemExit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     run(args)
 
 
