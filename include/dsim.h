@@ -82,7 +82,13 @@ extern "C" {
 typedef enum { DSIM_F64 = 0, DSIM_F32 = 1 } dsim_precision;
 
 /* entry selector for dsim_workspace_bytes / dsim_lds_bytes */
-typedef enum { DSIM_ENTRY_STEP = 0, DSIM_ENTRY_JACOBIAN = 1, DSIM_ENTRY_VJP = 2 } dsim_entry;
+typedef enum {
+    DSIM_ENTRY_STEP = 0,
+    DSIM_ENTRY_JACOBIAN = 1,
+    DSIM_ENTRY_VJP = 2,
+    DSIM_ENTRY_STEP_INTEGRATE = 3,
+    DSIM_ENTRY_STEP_INTEGRATE_VJP = 4
+} dsim_entry;
 
 /*
  * A batch of kinematic trees (Section II.C) with point contacts.
@@ -153,11 +159,14 @@ int32_t dsim_validate_host(const dsim_batch* host_batch, int32_t* bad_env);
 /* Checks of the parameter block alone (host). */
 int32_t dsim_validate_params(const dsim_params* params);
 
-/* Bytes of device workspace the given entry needs for this batch (0 when
- * everything fits on chip); `ws` arguments may be NULL when this is 0. */
+/* Bytes of device workspace the given entry needs for this batch.  Every
+ * entry keeps its working set on chip, so this is 0 and the `ws` arguments
+ * may be NULL; they are kept for ABI stability. */
 size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
 
-/* Bytes of on-chip (LDS) storage one environment team uses. */
+/* Bytes of on-chip (LDS) storage one environment team uses for `entry`
+ * (a dsim_entry).  A call whose team needs more than 160 KiB (the LDS of
+ * one gfx950 compute unit) returns DSIM_ERR_SIZE. */
 size_t dsim_lds_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
 
 /*
@@ -195,6 +204,45 @@ int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
                       void* v_next, void* lam, int8_t* mode, int32_t* status,
                       void* g_q, void* g_v, void* g_tau,
                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * The step followed by the position update q_next = q (+) dt v_next
+ * (symplectic Euler: the discrete motion of Section II.C advanced in
+ * position with the new velocity): a revolute angle adds dt v_next, a free
+ * flyer composes its placement with Exp(dt v_next) on the right and
+ * renormalises the quaternion.  q_next has the layout of q [sum n_q]; the
+ * other outputs are those of dsim_step.
+ */
+int32_t dsim_step_integrate(const dsim_batch* batch, const dsim_params* params,
+                            const void* q, const void* v, const void* tau,
+                            void* q_next, void* v_next, void* lam, int8_t* mode, int32_t* status,
+                            void* stream);
+
+/*
+ * Adjoint of dsim_step_integrate for one step of a rollout (reverse mode of
+ * Section III.A chained with the position update): given the adjoints
+ * a_qnext [sum n_v] (tangent, at q_next) and a_vnext [sum n_v] of the
+ * outputs, recomputes the step at (q, v, tau) and returns the adjoints of the
+ * inputs: a_q [sum n_v] (tangent, at q), a_v [sum n_v], g_tau [sum n_v].
+ * The step outputs (v_next, lam, mode, status) are written too.
+ */
+int32_t dsim_step_integrate_vjp(const dsim_batch* batch, const dsim_params* params,
+                                const void* q, const void* v, const void* tau,
+                                const void* a_qnext, const void* a_vnext,
+                                void* v_next, void* lam, int8_t* mode, int32_t* status,
+                                void* a_q, void* a_v, void* g_tau, void* stream);
+
+/*
+ * Maps a gradient in the tangent coordinates of q (g_tangent [sum n_v], as
+ * returned by the VJP entries) to the stored coordinates of q
+ * (g_ambient [sum n_q]): revolute entries copy; a free flyer gets
+ * R(quat) g_linear for the position and 2 quat * (g_angular, 0) for the
+ * quaternion, so that g_ambient . (d q / d delta) = g_tangent for the
+ * perturbation q (+) delta.  Needs only the body offsets and joint types of
+ * `batch`; `precision` is a dsim_precision.
+ */
+int32_t dsim_tangent_to_ambient(const dsim_batch* batch, int32_t precision, const void* q,
+                                const void* g_tangent, void* g_ambient, void* stream);
 
 #ifdef __cplusplus
 }

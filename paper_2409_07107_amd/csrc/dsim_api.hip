@@ -16,7 +16,6 @@ using namespace dsim;
 namespace {
 
 constexpr size_t kLdsLimit = 160 * 1024;  // bytes of LDS per workgroup on gfx950
-constexpr int kWsBlocks = 2048;           // workgroups in workspace mode
 
 template <class R>
 BatchView<R> view(const dsim_batch* b) {
@@ -80,11 +79,12 @@ int team_threads(const dsim_params* p) {
     return p->threads > 0 ? p->threads : 128;
 }
 
+// One workgroup (team) per environment; the team's whole working set is
+// carved from the dynamic LDS allocation.
 template <class R, int ENTRY>
 __global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims D, const R* q, const R* v,
-                                                  const R* tau, const R* gbar, R* v_next, R* lam, int8_t* mode,
-                                                  int32_t* status, R* o1, R* o2, R* o3, char* ws, size_t ws_stride,
-                                                  int use_lds) {
+                                                  const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
+                                                  int8_t* mode, int32_t* status, R* o1, R* o2, R* o3) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Team T;
     T.tid = threadIdx.x;
@@ -92,11 +92,50 @@ __global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims
     T.lane = threadIdx.x & 63;
     T.wave = threadIdx.x >> 6;
     T.wsize = 64;
-    char* base = use_lds ? smem : ws + size_t(blockIdx.x) * ws_stride;
     Env<R> E;
-    carve<R>(base, D, ENTRY, E);
-    for (int e = blockIdx.x; e < B.n_env; e += gridDim.x) {
-        run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, v_next, lam, mode, status, o1, o2, o3);
+    carve<R>(smem, D, ENTRY, E);
+    const int e = blockIdx.x;
+    run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3);
+}
+
+// Tangent gradient on q -> gradient on the stored coordinates of q: per body,
+// a revolute angle copies; a free flyer (q = p, quaternion) maps the
+// body-frame linear part by R(quat) and the angular part g to
+// 2 quat * (g, 0), the gradient whose pairing with the coordinate change
+// of q (+) d reproduces the tangent gradient for every d.
+template <class R>
+__global__ __launch_bounds__(64) void ambient_kernel(BatchView<R> B, const R* q, const R* gt, R* ga) {
+    const int e = blockIdx.x;
+    const int b0 = B.body_off[e], nb = B.body_off[e + 1] - b0;
+    const int q0 = B.cfg_off[e], d0 = B.dof_off[e];
+    // configuration and velocity offsets of each body follow from the joint
+    // types in body order: computed redundantly by every lane
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        int cfg = 0, dof = 0;
+        for (int i = 0; i < b; ++i) {
+            const bool ff = B.jtype[b0 + i] == 1;
+            cfg += ff ? 7 : 1;
+            dof += ff ? 6 : 1;
+        }
+        const R* qq = q + q0 + cfg;
+        const R* g = gt + d0 + dof;
+        R* o = ga + q0 + cfg;
+        if (B.jtype[b0 + b] == 1) {
+            const double x = qq[3], y = qq[4], z = qq[5], w = qq[6];
+            const double Rm[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                                  2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                                  2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)};
+            for (int i = 0; i < 3; ++i)
+                o[i] = R(Rm[3 * i] * double(g[0]) + Rm[3 * i + 1] * double(g[1]) + Rm[3 * i + 2] * double(g[2]));
+            const double gx = g[3], gy = g[4], gz = g[5];
+            // 2 (x y z w) * (gx gy gz 0)
+            o[3] = R(2 * (w * gx + (y * gz - z * gy)));
+            o[4] = R(2 * (w * gy + (z * gx - x * gz)));
+            o[5] = R(2 * (w * gz + (x * gy - y * gx)));
+            o[6] = R(-2 * (x * gx + y * gy + z * gz));
+        } else {
+            o[0] = g[0];
+        }
     }
 }
 
@@ -118,47 +157,38 @@ int check_common(const dsim_batch* b, const dsim_params* p) {
 
 template <class R, int ENTRY>
 int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
-           const void* gbar, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1, void* o2, void* o3,
-           void* ws, size_t ws_bytes, void* stream) {
+           const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
+           void* o2, void* o3, void* stream) {
     if (b->n_env == 0) return DSIM_SUCCESS;
     const size_t bytes = team_bytes(b, p, ENTRY);
-    const bool use_lds = bytes <= kLdsLimit;
+    if (bytes > kLdsLimit) return DSIM_ERR_SIZE;  // the team's working set must fit in LDS
     const int threads = team_threads(p);
-    int grid = b->n_env;
-    size_t stride = 0;
-    if (!use_lds) {
-        grid = b->n_env < kWsBlocks ? b->n_env : kWsBlocks;
-        stride = (bytes + 255) & ~size_t(255);
-        if (!ws || ws_bytes < stride * size_t(grid)) return DSIM_ERR_WORKSPACE;
-    }
     auto kern = env_kernel<R, ENTRY>;
-    const unsigned lds = use_lds ? unsigned(bytes) : 0u;
+    const unsigned lds = unsigned(bytes);
     if (lds > 64 * 1024) {
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 int(lds)) != hipSuccess)
             return DSIM_ERR_LAUNCH;
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, static_cast<hipStream_t>(stream), view<R>(b),
+    hipLaunchKernelGGL(kern, dim3(b->n_env), dim3(threads), lds, static_cast<hipStream_t>(stream), view<R>(b),
                        params_of(p), dims_of(b), static_cast<const R*>(q), static_cast<const R*>(v),
-                       static_cast<const R*>(tau), static_cast<const R*>(gbar), static_cast<R*>(v_next),
-                       static_cast<R*>(lam), mode, status, static_cast<R*>(o1), static_cast<R*>(o2),
-                       static_cast<R*>(o3), static_cast<char*>(ws), stride, use_lds ? 1 : 0);
+                       static_cast<const R*>(tau), static_cast<const R*>(gbar), static_cast<const R*>(gbar2),
+                       static_cast<R*>(v_next), static_cast<R*>(lam), mode, status, static_cast<R*>(o1),
+                       static_cast<R*>(o2), static_cast<R*>(o3));
     return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
 }
 
 template <int ENTRY>
 int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
-             const void* gbar, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1, void* o2, void* o3,
-             void* ws, size_t ws_bytes, void* stream) {
+             const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
+             void* o2, void* o3, void* stream) {
     int rc = check_common(b, p);
     if (rc) return rc;
     if (b->n_env == 0) return DSIM_SUCCESS;
     if (!q || !v || !tau || !v_next || !status || !mode || !lam) return DSIM_ERR_ARG;
     if (p->precision == DSIM_F32)
-        return launch<float, ENTRY>(b, p, q, v, tau, gbar, v_next, lam, mode, status, o1, o2, o3, ws, ws_bytes,
-                                    stream);
-    return launch<double, ENTRY>(b, p, q, v, tau, gbar, v_next, lam, mode, status, o1, o2, o3, ws, ws_bytes,
-                                 stream);
+        return launch<float, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, stream);
+    return launch<double, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, stream);
 }
 
 }  // namespace
@@ -292,39 +322,76 @@ int32_t dsim_validate_host(const dsim_batch* b, int32_t* bad_env) {
 }
 
 size_t dsim_lds_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) {
-    if (!b || !p || entry < 0 || entry > 2) return 0;
+    if (!b || !p || entry < 0 || entry > DSIM_ENTRY_STEP_INTEGRATE_VJP) return 0;
     return team_bytes(b, p, entry);
 }
 
 size_t dsim_workspace_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) {
-    if (!b || !p || entry < 0 || entry > 2 || b->n_env <= 0) return 0;
-    const size_t bytes = team_bytes(b, p, entry);
-    if (bytes <= kLdsLimit) return 0;
-    const size_t stride = (bytes + 255) & ~size_t(255);
-    const int grid = b->n_env < kWsBlocks ? b->n_env : kWsBlocks;
-    return stride * size_t(grid);
+    (void)b;
+    (void)p;
+    (void)entry;
+    return 0;  // every entry runs in LDS
 }
 
 int32_t dsim_step(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
                   void* v_next, void* lam, int8_t* mode, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-    return dispatch<ENTRY_STEP>(b, p, q, v, tau, nullptr, v_next, lam, mode, status, nullptr, nullptr, nullptr, ws,
-                                ws_bytes, stream);
+    (void)ws;
+    (void)ws_bytes;
+    return dispatch<ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr, nullptr,
+                                nullptr, stream);
 }
 
 int32_t dsim_step_jacobian(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
                            void* v_next, void* lam, int8_t* mode, int32_t* status, void* dvdq, void* dvdv,
                            void* dvdtau, void* ws, size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
     if (!dvdq || !dvdv || !dvdtau || (b && b->n_env > 0 && !b->jac_off)) return DSIM_ERR_ARG;
-    return dispatch<ENTRY_JAC>(b, p, q, v, tau, nullptr, v_next, lam, mode, status, dvdq, dvdv, dvdtau, ws,
-                               ws_bytes, stream);
+    return dispatch<ENTRY_JAC>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, dvdq, dvdv, dvdtau,
+                               stream);
 }
 
 int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
                       const void* g_vnext, void* v_next, void* lam, int8_t* mode, int32_t* status, void* g_q,
                       void* g_v, void* g_tau, void* ws, size_t ws_bytes, void* stream) {
+    (void)ws;
+    (void)ws_bytes;
     if (!g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
-    return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, v_next, lam, mode, status, g_q, g_v, g_tau, ws, ws_bytes,
+    return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, nullptr, v_next, lam, mode, status, g_q, g_v, g_tau,
                                stream);
+}
+
+int32_t dsim_step_integrate(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                            const void* tau, void* q_next, void* v_next, void* lam, int8_t* mode, int32_t* status,
+                            void* stream) {
+    if (!q_next) return DSIM_ERR_ARG;
+    return dispatch<ENTRY_SINT>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, q_next, nullptr,
+                                nullptr, stream);
+}
+
+int32_t dsim_step_integrate_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                                const void* tau, const void* a_qnext, const void* a_vnext, void* v_next, void* lam,
+                                int8_t* mode, int32_t* status, void* a_q, void* a_v, void* g_tau, void* stream) {
+    if (!a_qnext || !a_vnext || !a_q || !a_v || !g_tau) return DSIM_ERR_ARG;
+    return dispatch<ENTRY_RVJP>(b, p, q, v, tau, a_vnext, a_qnext, v_next, lam, mode, status, a_q, a_v, g_tau,
+                                stream);
+}
+
+int32_t dsim_tangent_to_ambient(const dsim_batch* b, int32_t precision, const void* q, const void* g_tangent,
+                                void* g_ambient, void* stream) {
+    if (!b || b->n_env < 0 || (precision != DSIM_F32 && precision != DSIM_F64)) return DSIM_ERR_ARG;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !g_tangent || !g_ambient || !b->body_off || !b->dof_off || !b->cfg_off || !b->jtype)
+        return DSIM_ERR_ARG;
+    if (precision == DSIM_F32)
+        hipLaunchKernelGGL(ambient_kernel<float>, dim3(b->n_env), dim3(64), 0, static_cast<hipStream_t>(stream),
+                           view<float>(b), static_cast<const float*>(q), static_cast<const float*>(g_tangent),
+                           static_cast<float*>(g_ambient));
+    else
+        hipLaunchKernelGGL(ambient_kernel<double>, dim3(b->n_env), dim3(64), 0, static_cast<hipStream_t>(stream),
+                           view<double>(b), static_cast<const double*>(q), static_cast<const double*>(g_tangent),
+                           static_cast<double*>(g_ambient));
+    return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
 }
 
 }  // extern "C"

@@ -58,7 +58,12 @@ struct Team {
 // status bits and modes (mirror include/dsim.h)
 enum { ST_NCP = 1, ST_RANK = 2, ST_DEGEN = 4, ST_NONFINITE = 8, ST_POLISH = 16 };
 enum { BRK = 0, STK = 1, SLD = 2 };
-enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2 };
+// entries: the step; the step and its full Jacobian; the step and its VJP;
+// the step followed by q+ = q (+) dt v+; the adjoint of that fused map
+enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4 };
+DSIM_HD inline bool entry_has_derivative(int entry) {
+    return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP;
+}
 
 template <class R>
 struct BatchView {
@@ -162,6 +167,7 @@ struct Env {
     double *Rw, *pw, *S, *V, *Vp, *Acc, *Fc, *Iw, *Ic, *Bc, *Ec, *xw, *org;
     double *v, *tau, *bias, *af, *vf, *vn, *ap, *Mx, *Mi;
     double *IcS, *BtS, *EtS, *aj, *wj, *cj, *Yq, *Yv;
+    double* gint;  // adjoint of q carried through the position update
     double* scr;  // FP64 solve scratch, max(K, NV) x NV
     // working-precision quantities
     R *mu, *Winv, *J, *KT, *G, *g, *Lam, *sig, *Lam0;
@@ -258,8 +264,9 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.ytmp = take<double>(p, K, tot);
     E.dsig = take<double>(p, K, tot);
     E.dsc = take<double>(p, 4, tot);
-    if (entry != ENTRY_STEP) {
+    if (entry_has_derivative(entry)) {
         E.Vp = take<double>(p, 6 * NB, tot);
+        E.gint = take<double>(p, NV, tot);
         // union: {per-dof vectors, composites} | Q
         const size_t nvec = size_t(45) * NV + size_t(54) * NB;
         const size_t u1 = nvec * sizeof(double) > size_t(NN) * sizeof(R) ? nvec * sizeof(double) : size_t(NN) * sizeof(R);

@@ -377,15 +377,153 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
     T.sync();
 }
 
+// --------------------------------------------------------------------------
+// position update q+ = q (+) dt v+ (symplectic Euler) and its adjoint
+// --------------------------------------------------------------------------
+
+// sin(t)/t, (1 - cos t)/t^2, (t - sin t)/t^3 and sin(t/2)/t for t = |w|,
+// by their Taylor series near 0 (truncation below 1e-17 for t < 1e-2).
+DSIM_HD inline void exp_coeffs(const double* w, double& a, double& b, double& c, double& h) {
+    const double t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    if (t2 < 1e-4) {
+        a = 1.0 - t2 / 6.0 * (1.0 - t2 / 20.0 * (1.0 - t2 / 42.0));
+        b = 0.5 - t2 / 24.0 * (1.0 - t2 / 30.0 * (1.0 - t2 / 56.0));
+        c = 1.0 / 6.0 - t2 / 120.0 * (1.0 - t2 / 42.0 * (1.0 - t2 / 72.0));
+        h = 0.5 - t2 / 48.0 * (1.0 - t2 / 80.0 * (1.0 - t2 / 168.0));
+        return;
+    }
+    const double t = sqrt(t2);
+    a = sin(t) / t;
+    b = (1.0 - cos(t)) / t2;
+    c = (t - sin(t)) / (t2 * t);
+    h = sin(0.5 * t) / t;
+}
+
+// X = Exp(xi) for a body twist xi = (linear rho, angular phi): rotation Rx
+// (row-major) and translation tx = V(phi) rho.
+DSIM_HD inline void exp_se3(const double* xi, double* Rx, double* tx) {
+    const double* rho = xi;
+    const double* phi = xi + 3;
+    double a, b, c, h;
+    exp_coeffs(phi, a, b, c, h);
+    const double K[9] = {0, -phi[2], phi[1], phi[2], 0, -phi[0], -phi[1], phi[0], 0};
+    double K2[9];
+    mat3mul(K, K, K2);
+    double V[9];
+    for (int i = 0; i < 9; ++i) {
+        const double id = (i % 4 == 0) ? 1.0 : 0.0;
+        Rx[i] = id + a * K[i] + b * K2[i];
+        V[i] = id + b * K[i] + c * K2[i];
+    }
+    mat3vec(V, rho, tx);
+}
+
+// q+ = q (+) dt v+ for every joint of the environment (v+ = E.vn).  A free
+// flyer composes its placement with Exp(dt v+) on the right: p+ = p + R t,
+// quat+ = quat * exp(dt omega) (renormalised); a revolute angle adds dt v+.
+template <class R>
+DSIM_HD void integrate(const Team& T, Env<R>& E, const Params& P, const R* q, R* qn) {
+    for (int b = T.tid; b < E.nb; b += T.nt) {
+        const int c0 = E.q0 + E.cfg0[b], d0 = E.dof0[b];
+        if (E.jtype[b] == 1) {
+            double xi[6], Rx[9], tx[3];
+            for (int i = 0; i < 6; ++i) xi[i] = P.dt * E.vn[d0 + i];
+            exp_se3(xi, Rx, tx);
+            double a, bb, c, h;
+            exp_coeffs(xi + 3, a, bb, c, h);
+            const double* Rw = E.Rw + 9 * b;  // R(quat) from the kinematics
+            double dp[3];
+            mat3vec(Rw, tx, dp);
+            for (int i = 0; i < 3; ++i) qn[c0 + i] = R(double(q[c0 + i]) + dp[i]);
+            const double x = q[c0 + 3], y = q[c0 + 4], z = q[c0 + 5], w = q[c0 + 6];
+            const double ex = h * xi[3], ey = h * xi[4], ez = h * xi[5];
+            const double ew = cos(0.5 * sqrt(xi[3] * xi[3] + xi[4] * xi[4] + xi[5] * xi[5]));
+            // quaternion product (x y z w) * (ex ey ez ew)
+            double nx = w * ex + ew * x + (y * ez - z * ey);
+            double ny = w * ey + ew * y + (z * ex - x * ez);
+            double nz = w * ez + ew * z + (x * ey - y * ex);
+            double nw = w * ew - (x * ex + y * ey + z * ez);
+            const double inv = 1.0 / sqrt(nx * nx + ny * ny + nz * nz + nw * nw);
+            qn[c0 + 3] = R(nx * inv);
+            qn[c0 + 4] = R(ny * inv);
+            qn[c0 + 5] = R(nz * inv);
+            qn[c0 + 6] = R(nw * inv);
+        } else {
+            qn[c0] = R(double(q[c0]) + P.dt * E.vn[d0]);
+        }
+    }
+    T.sync();
+}
+
+// Adjoint of the position update at (q, v+) for a tangent adjoint aq of q+:
+// with X = Exp(xi), xi = dt v+, a perturbation q (+) d and v+ + dv gives
+// q+ (+) (Ad_{X^-1} d + dt Jr(xi) dv) to first order, Jr the right Jacobian
+// of the exponential, Jr(xi) = sum_k (-ad_xi)^k / (k+1)!.  Adds
+// dt Jr^T aq to gv (the adjoint of v+) and writes Ad_{X^-1}^T aq to gq.
+template <class R>
+DSIM_HD void integrate_adjoint(const Team& T, Env<R>& E, const Params& P, const R* aq, double* gv, double* gq) {
+    for (int b = T.tid; b < E.nb; b += T.nt) {
+        const int d0 = E.dof0[b];
+        if (E.jtype[b] == 1) {
+            double xi[6], a[6], Rx[9], tx[3];
+            for (int i = 0; i < 6; ++i) {
+                xi[i] = P.dt * E.vn[d0 + i];
+                a[i] = double(aq[E.d0 + d0 + i]);
+            }
+            exp_se3(xi, Rx, tx);
+            // Ad_{X^-1}^T a = (Rx a_lin, tx x (Rx a_lin) + Rx a_ang)
+            double rl[3], ra[3], txr[3];
+            mat3vec(Rx, a, rl);
+            mat3vec(Rx, a + 3, ra);
+            cross3(tx, rl, txr);
+            for (int i = 0; i < 3; ++i) {
+                gq[d0 + i] = rl[i];
+                gq[d0 + 3 + i] = txr[i] + ra[i];
+            }
+            // Jr^T a = sum_k M^k a / (k+1)!, M = (-ad_xi)^T:
+            // M (x_lin, x_ang) = (phi x x_lin, rho x x_lin + phi x x_ang)
+            double term[6], sum[6];
+            for (int i = 0; i < 6; ++i) term[i] = sum[i] = a[i];
+            double na = 0;
+            for (int i = 0; i < 6; ++i) na = fmax(na, fabs(a[i]));
+            for (int kk = 1; kk < 60; ++kk) {
+                double l[3], r1[3], r2[3];
+                cross3(xi + 3, term, l);
+                cross3(xi, term, r1);
+                cross3(xi + 3, term + 3, r2);
+                double tm = 0;
+                for (int i = 0; i < 3; ++i) {
+                    term[i] = l[i] / (kk + 1);
+                    term[3 + i] = (r1[i] + r2[i]) / (kk + 1);
+                    tm = fmax(tm, fmax(fabs(term[i]), fabs(term[3 + i])));
+                }
+                for (int i = 0; i < 6; ++i) sum[i] += term[i];
+                if (tm <= 1e-18 * na) break;
+            }
+            for (int i = 0; i < 6; ++i) gv[d0 + i] += P.dt * sum[i];
+        } else {
+            const double a = double(aq[E.d0 + d0]);
+            gq[d0] = a;
+            gv[d0] += P.dt * a;
+        }
+    }
+    T.sync();
+}
+
 // Reverse mode: the transpose of the Jacobian above applied to gbar,
 //   tg = T^T gbar = -B^T A^-T C^T (K^T gbar),  pg = P^T gbar = gbar + J^T tg,
 //   qg = Q^T gbar = M^-1 pg,
 //   g_tau = dt qg,  g_v = pg - dt dtau/dv^T qg,  g_q = -dt dtau/dq^T qg + E^T tg.
 // The transposed solve is the exact transpose of the basic-solution operator
 // of the forward derivative, so both agree for rank-deficient A.
+//
+// With aqn != nullptr (the adjoint of the fused step and position update),
+// gbar is the adjoint of v+ coming from later steps and aqn the tangent
+// adjoint of q+: the adjoint of the position update is applied first and its
+// q part added to gq.
 template <class R>
-DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* gbar, R* gq, R* gv,
-                 R* gtau) {
+DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* gbar, const R* aqn,
+                 R* gq, R* gv, R* gtau) {
     const int n = E.nv, k = E.k, m = E.hdr[1], rank = E.hdr[4];
     derivative_partials(T, E, P);
     double* gb = E.bias;  // gbar (the bias is no longer needed)
@@ -394,6 +532,7 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
     double* tg = E.scr;   // T^T gbar (k)
     for (int i = T.tid; i < n; i += T.nt) gb[i] = double(gbar[E.d0 + i]);
     T.sync();
+    if (aqn) integrate_adjoint(T, E, P, aqn, gb, E.gint);
     if (T.tid == 0) {
         double* sp = E.rhs;
         double* z = E.ytmp;
@@ -445,7 +584,7 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
             sv += double(E.dTv[l * n + j]) * pg[l];
         }
         for (int r = 0; r < k; ++r) se += double(E.E[r * n + j]) * tg[r];
-        gq[E.d0 + j] = R(-P.dt * sq + se);
+        gq[E.d0 + j] = R(-P.dt * sq + se + (aqn ? E.gint[j] : 0.0));
         gv[E.d0 + j] = R(pk[j] - P.dt * sv);
         gtau[E.d0 + j] = R(P.dt * pg[j]);
     }
@@ -455,13 +594,15 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
 // Full pipeline of one environment.
 template <class R>
 DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, int entry, int e,
-                     const R* q, const R* v, const R* tau, const R* gbar, R* v_next, R* lam, int8_t* mode,
-                     int32_t* status, R* o1, R* o2, R* o3) {
+                     const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
+                     int8_t* mode, int32_t* status, R* o1, R* o2, R* o3) {
     load_env(T, E, B, e, q, v, tau);
     step_forward(T, E, B, P, q);
     write_step(T, E, v_next, lam, mode, status);
     if (entry == ENTRY_JAC) jacobian(T, E, B, P, o1, o2, o3);
-    if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, o1, o2, o3);
+    if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
+    if (entry == ENTRY_SINT) integrate(T, E, P, q, o1);
+    if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
     T.sync();
 }
 

@@ -17,13 +17,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsim.so")
 
 F64, F32 = 0, 1
-ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP = 0, 1, 2
+ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP, ENTRY_STEP_INTEGRATE, ENTRY_STEP_INTEGRATE_VJP = 0, 1, 2, 3, 4
 ST_NCP_NOT_CONVERGED, ST_RANK_DEFICIENT, ST_MODE_DEGENERATE, ST_NONFINITE, ST_POLISH_FAILED = 1, 2, 4, 8, 16
 MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
 
 SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim_validate_host",
            "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
-           "dsim_step_jacobian", "dsim_step_vjp")
+           "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
+           "dsim_tangent_to_ambient")
 
 _vp = ctypes.c_void_p
 
@@ -74,6 +75,13 @@ def lib():
         L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp.restype = ctypes.c_int32
+        L.dsim_step_integrate.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + [_vp]
+        L.dsim_step_integrate.restype = ctypes.c_int32
+        L.dsim_step_integrate_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
+            [_vp]
+        L.dsim_step_integrate_vjp.restype = ctypes.c_int32
+        L.dsim_tangent_to_ambient.argtypes = [ctypes.POINTER(CBatch), ctypes.c_int32, _vp, _vp, _vp, _vp]
+        L.dsim_tangent_to_ambient.restype = ctypes.c_int32
         _LIB = L
     return _LIB
 
@@ -275,3 +283,49 @@ def split_jacobian(db: DeviceBatch, out, e: int):
     nv = int(db.batch.dof_off[e + 1] - db.batch.dof_off[e])
     blocks = [out[k][jo[e]:jo[e + 1]].reshape(nv, nv).double().cpu().numpy() for k in ("dvdq", "dvdv", "dvdtau")]
     return np.concatenate(blocks, axis=1)
+
+
+def step_integrate(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+    """The step followed by q+ = q (+) dt v+: adds "q_next" to the step outputs."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        out["q_next"] = torch.empty_like(q)
+    _check(lib().dsim_step_integrate(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                                     _ptr(out["q_next"]), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                     _ptr(out["mode"]), _ptr(out["status"]), ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_integrate_vjp(db: DeviceBatch, a_qnext, a_vnext, q=None, v=None, tau=None, p: CParams | None = None,
+                       out=None):
+    """Adjoint of step_integrate: tangent adjoint a_qnext of q+ and adjoint
+    a_vnext of v+ -> "a_q" (tangent), "a_v", "g_tau" (plus the step outputs)."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        for k in ("a_q", "a_v", "g_tau"):
+            out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
+    _check(lib().dsim_step_integrate_vjp(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                                         _ptr(a_qnext), _ptr(a_vnext), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                         _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["a_q"]),
+                                         _ptr(out["a_v"]), _ptr(out["g_tau"]), ctypes.c_void_p(_stream())))
+    return out
+
+
+def tangent_to_ambient(db: DeviceBatch, q, g_tangent, out=None):
+    """Tangent gradient on q [sum n_v] -> gradient on the stored q [sum n_q]."""
+    import torch
+    if out is None:
+        out = torch.empty_like(q)
+    _check(lib().dsim_tangent_to_ambient(ctypes.byref(db.c), db.precision, _ptr(q), _ptr(g_tangent), _ptr(out),
+                                         ctypes.c_void_p(_stream())))
+    return out

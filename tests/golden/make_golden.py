@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from paper_2409_07107_amd import scenes  # noqa: E402
-from oracle import derivative, step  # noqa: E402
+from oracle import derivative, rollout, step  # noqa: E402
 
 # name -> (workload, n_env of the batch, seed, env indices to store)
 SETS = {
@@ -32,6 +32,12 @@ SETS = {
     "arm7_4096_sample": ("arm7", 4096, 0, [0, 1, 2, 63, 64, 1000, 2047, 2048, 3001, 4093, 4094, 4095]),
     "tree36_16384_sample": ("tree36", 16384, 0, [0, 1, 2, 3, 255, 256, 4097, 8191, 8192, 12000,
                                                    16379, 16380, 16381, 16382, 16383]),
+}
+
+# rollouts: name -> (workload, n_env, seed, steps, gap_mode, generator options)
+ROLLOUTS = {
+    "rollout_cube": ("cube", 4, 21, 8, 1, {"v_std": 0.3}),
+    "rollout_tree36": ("tree36", 3, 22, 4, 0, {}),
 }
 
 _BATCH = None
@@ -63,6 +69,43 @@ def make(name):
     print(name, "ok", int(out["ok"].sum()), "/", len(envs), "unique", int(out["unique"].sum()), flush=True)
 
 
+def rollout_inputs(name):
+    """The seeded batch, torque sequences (T x n_v per env) and base targets
+    of a rollout set (inputs only; shared with the GPU test)."""
+    wl, n, seed, T, gap_mode, kw = ROLLOUTS[name]
+    batch = scenes.make(wl, n, seed=seed, **kw)
+    batch.gap_mode = gap_mode
+    rng = np.random.default_rng(seed + 1000)
+    taus, targets = [], []
+    for e in range(n):
+        nv = int(batch.dof_off[e + 1] - batch.dof_off[e])
+        taus.append(rng.normal(scale=0.5, size=(T, nv)))
+        targets.append(batch.q[batch.cfg_off[e]:batch.cfg_off[e] + 3] + rng.normal(scale=0.1, size=3))
+    return batch, np.array(taus), np.array(targets)
+
+
+def _roll(args):
+    name, e = args
+    batch, taus, targets = rollout_inputs(name)
+    r = rollout.rollout_gradient(batch.env(e), taus[e], targets[e])
+    return dict(loss=r["loss"], grad=r["grad"], qT=r["q"][-1], vT=r["v"][-1], ok=r["ok"], margin=r["margin"])
+
+
+def make_rollout(name):
+    wl, n, seed, T, gap_mode, kw = ROLLOUTS[name]
+    batch, taus, targets = rollout_inputs(name)
+    with Pool(min(8, n)) as p:
+        res = p.map(_roll, [(name, e) for e in range(n)])
+    out = dict(workload=wl, n_env=n, seed=seed, steps=T, gap_mode=gap_mode, taus=taus, targets=targets)
+    for key in ("loss", "grad", "qT", "vT", "ok", "margin"):
+        out[key] = np.array([r[key] for r in res])
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), **out)
+    print(name, "ok", int(out["ok"].sum()), "/", n, "min margin", float(out["margin"].min()), flush=True)
+
+
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(SETS)):
-        make(name)
+    for name in (sys.argv[1:] or list(SETS) + list(ROLLOUTS)):
+        if name in ROLLOUTS:
+            make_rollout(name)
+        else:
+            make(name)
