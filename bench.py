@@ -188,6 +188,59 @@ def run(args):
     print(json.dumps(line), flush=True)
 
 
+def run_mixed(args):
+    """The ragged workload: 8192 random trees (7-40 dof, 0-16 contacts) in
+    the FP32 form, step + full Jacobian, launched as an autotuned plan (size
+    classes, start order, team sizes) captured in one graph and replayed."""
+    import torch
+    from paper_2409_07107_amd import autotune, dsim, scenes
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    batch = scenes.make("mixed", 8192, seed=0)
+    db = dsim.DeviceBatch(batch, precision=dsim.F32)
+    p = db.params()
+    plan, table = autotune.autotune(db, p, dsim.ENTRY_JACOBIAN, reps=2,
+                                    log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
+    out = autotune.new_outputs(db, dsim.ENTRY_JACOBIAN)
+    g = autotune.GraphLaunch(db, plan, p, out)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record()
+        g.replay()
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    graph_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    status = out["status"].cpu().numpy()
+    modes = out["mode"].cpu().numpy()[:batch.contact_off[-1]]
+    f32, f64 = algorithmic_flops(batch, out["mode"].cpu().numpy(), p.ncp_sweeps)
+    achieved = (f32 + f64) / (graph_ms * 1e-3) / 1e12
+    value = batch.n_env * args.steps / wall
+    line = {
+        "metric": "step-derivative evals/sec (ragged trees 7-40 dof, 0-16 contacts), FP32 planned graph launch",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mixed: 8192 random trees, n_v ~ U{7..40}, half floating, 1-5 branches, "
+                               "n_c ~ U{0..16} (4-point patches + single points), mu ~ U(0.2, 1.2); step + full "
+                               "Jacobian per env", "n_env": batch.n_env, "seed": 0,
+                   "plan": plan.describe()},
+        "mode_mix": {"break": float(np.mean(modes == 0)), "stick": float(np.mean(modes == 1)),
+                     "slide": float(np.mean(modes == 2))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None, "kernel": "graph of env_kernel<float, "
+                     "jacobian> class launches", "kernel_ms": graph_ms},
+        "autotune": table,
+        "status_flagged": int(((status & 17) != 0).sum()),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_probe(nbytes):
     """One plain elementwise copy kernel (dst = src * 1 in FP32) over nbytes:
     the reference reading of the HBM byte counters (FETCH_SIZE, WRITE_SIZE)
@@ -209,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-f32", action="store_true",
                     help="time only the FP32 launch and print no JSON line (for profiler runs)")
+    ap.add_argument("--workload", choices=("tree36", "mixed"), default="tree36",
+                    help="tree36 (the headline line) or the ragged mixed batch")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run one plain copy of BYTES and exit (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +273,9 @@ def main():
         raise SystemExit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "mixed":
+        run_mixed(args)
         return
     run(args)
 

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define DSIM_ABI_VERSION 1
+#define DSIM_ABI_VERSION 2
 
 /* return codes */
 #define DSIM_SUCCESS 0
@@ -64,6 +64,7 @@ extern "C" {
 #define DSIM_ST_MODE_DEGENERATE 4    /* a contact within mode_eps of a mode switch */
 #define DSIM_ST_NONFINITE 8          /* a NaN or Inf reached the outputs */
 #define DSIM_ST_POLISH_FAILED 16     /* Newton refinement left the mode set */
+#define DSIM_ST_SIZE_EXCEEDED 32     /* larger than the launch's max_* sizes: not computed */
 
 /* contact modes written to `mode` (Section III.B) */
 #define DSIM_MODE_BREAK 0
@@ -113,8 +114,15 @@ typedef enum {
  * jac_off (n_env + 1 entries) is the prefix sum of n_v^2, the offsets of the
  * per-environment Jacobian blocks (needed by dsim_step_jacobian only; may be
  * NULL otherwise).
- * The max_* fields must bound every environment (they size the on-chip
- * buffers); n_env may be 0.
+ * order (device, optional): when non-NULL, a launch processes only the
+ *   n_order environments order[0 .. n_order-1] (indices into 0 .. n_env-1,
+ *   in the order the hardware should start them; out-of-range entries are
+ *   skipped).  With a sub-list the max_* fields need to bound only the listed
+ *   environments: this is how a ragged batch is split into size classes
+ *   (each launch sized for its class) and how expensive environments are
+ *   started first.
+ * The max_* fields must bound every processed environment (they size the
+ * on-chip buffers); n_env may be 0.
  */
 typedef struct dsim_batch {
     int32_t n_env;
@@ -122,6 +130,8 @@ typedef struct dsim_batch {
     const int32_t *body_off, *dof_off, *cfg_off, *contact_off, *jac_off;
     const int32_t *parent, *jtype, *cbody;
     const void *axis, *jrot, *jpos, *mass, *com, *inertia, *cpoint, *mu;
+    int32_t n_order;
+    const int32_t* order;
 } dsim_batch;
 
 typedef struct dsim_params {
@@ -144,6 +154,10 @@ typedef struct dsim_params {
 void dsim_default_params(dsim_params* p, int32_t precision);
 
 int32_t dsim_abi_version(void);
+
+/* sizeof(dsim_batch) for which == 0, sizeof(dsim_params) for which == 1
+ * (0 otherwise): lets a binding check its mirror of the structs. */
+size_t dsim_struct_size(int32_t which);
 const char* dsim_error_string(int32_t code);
 
 /*

@@ -117,11 +117,16 @@ def _slide_candidates(W, b, mu, nsample=720):
 
 
 def local_solve(W, b, mu):
-    """Exact solution of the one-contact NCP sigma = W Lam + b (W SPD).
-    Returns (Lam, mode)."""
+    """Exact solution of the one-contact NCP sigma = W Lam + b (W SPSD).
+    Returns (Lam, mode).  When the point cannot move in every direction, W
+    is singular and the sticking impulse is not unique; the min-norm one is
+    taken (any of them gives the same velocities)."""
     if b[2] >= 0.0:
         return np.zeros(3), BRK
-    lam = -np.linalg.solve(W, b)
+    try:
+        lam = -np.linalg.solve(W, b)
+    except np.linalg.LinAlgError:
+        lam = -np.linalg.lstsq(W, b, rcond=None)[0]
     if lam[2] > 0 and np.hypot(lam[0], lam[1]) <= mu * lam[2]:
         return lam, STK
     cands = _slide_candidates(W, b, mu)

@@ -20,7 +20,7 @@ class DiffStep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q, v, tau, db, p):
         for name, t in (("q", q), ("v", v), ("tau", tau)):
-            if t.dtype != db.dtype or not t.is_contiguous() or t.device != db.device:
+            if t.dtype != db.dtype or not t.is_contiguous() or t.device.type != db.device.type:
                 raise ValueError(f"{name} must be a contiguous {db.dtype} tensor on {db.device}")
         out = dsim.step(db, q.detach(), v.detach(), tau.detach(), p)
         ctx.save_for_backward(q.detach(), v.detach(), tau.detach())

@@ -37,6 +37,7 @@ BatchView<R> view(const dsim_batch* b) {
     v.inertia = static_cast<const R*>(b->inertia);
     v.cpoint = static_cast<const R*>(b->cpoint);
     v.mu = static_cast<const R*>(b->mu);
+    v.order = b->order;
     return v;
 }
 
@@ -92,9 +93,16 @@ __global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims
     T.lane = threadIdx.x & 63;
     T.wave = threadIdx.x >> 6;
     T.wsize = 64;
+    const int e = B.order ? B.order[blockIdx.x] : int(blockIdx.x);
+    if (e < 0 || e >= B.n_env) return;  // the whole workgroup skips an invalid list entry
+    // an environment larger than the launch's buffers is not computed
+    if (B.body_off[e + 1] - B.body_off[e] > D.NB || B.dof_off[e + 1] - B.dof_off[e] > D.NV ||
+        B.contact_off[e + 1] - B.contact_off[e] > D.NC) {
+        if (threadIdx.x == 0) status[e] = ST_SIZE;
+        return;
+    }
     Env<R> E;
     carve<R>(smem, D, ENTRY, E);
-    const int e = blockIdx.x;
     run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3);
 }
 
@@ -170,7 +178,9 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
                                 int(lds)) != hipSuccess)
             return DSIM_ERR_LAUNCH;
     }
-    hipLaunchKernelGGL(kern, dim3(b->n_env), dim3(threads), lds, static_cast<hipStream_t>(stream), view<R>(b),
+    const int grid = b->order ? b->n_order : b->n_env;
+    if (grid <= 0) return DSIM_SUCCESS;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, static_cast<hipStream_t>(stream), view<R>(b),
                        params_of(p), dims_of(b), static_cast<const R*>(q), static_cast<const R*>(v),
                        static_cast<const R*>(tau), static_cast<const R*>(gbar), static_cast<const R*>(gbar2),
                        static_cast<R*>(v_next), static_cast<R*>(lam), mode, status, static_cast<R*>(o1),
@@ -220,6 +230,10 @@ void dsim_default_params(dsim_params* p, int32_t precision) {
 }
 
 int32_t dsim_abi_version(void) { return DSIM_ABI_VERSION; }
+
+size_t dsim_struct_size(int32_t which) {
+    return which == 0 ? sizeof(dsim_batch) : which == 1 ? sizeof(dsim_params) : 0;
+}
 
 const char* dsim_error_string(int32_t code) {
     switch (code) {

@@ -56,7 +56,7 @@ struct Team {
 };
 
 // status bits and modes (mirror include/dsim.h)
-enum { ST_NCP = 1, ST_RANK = 2, ST_DEGEN = 4, ST_NONFINITE = 8, ST_POLISH = 16 };
+enum { ST_NCP = 1, ST_RANK = 2, ST_DEGEN = 4, ST_NONFINITE = 8, ST_POLISH = 16, ST_SIZE = 32 };
 enum { BRK = 0, STK = 1, SLD = 2 };
 // entries: the step; the step and its full Jacobian; the step and its VJP;
 // the step followed by q+ = q (+) dt v+; the adjoint of that fused map
@@ -71,6 +71,7 @@ struct BatchView {
     const int32_t *body_off, *dof_off, *cfg_off, *contact_off, *jac_off;
     const int32_t *parent, *jtype, *cbody;
     const R *axis, *jrot, *jpos, *mass, *com, *inertia, *cpoint, *mu;
+    const int32_t* order;  // optional launch list (block index -> environment)
 };
 
 struct Params {
@@ -171,7 +172,7 @@ struct Env {
     double* scr;  // FP64 solve scratch, max(K, NV) x NV
     // working-precision quantities
     R *mu, *Winv, *J, *KT, *G, *g, *Lam, *sig, *Lam0;
-    R *dTq, *dTv, *E, *Minv, *T, *P, *Q;
+    R *dTq, *dTv, *E, *T, *P, *Q;
     // FP64 contact system; reduced variables: row and column vectors, diagonal
     double *vrow, *vcol, *vdiag;
     double *Gd, *gd, *Ld, *Ld1, *dfr;
@@ -230,21 +231,49 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.vf = take<double>(p, NV, tot);
     E.vn = take<double>(p, NV, tot);
     E.ap = take<double>(p, NV, tot);
-    // Buffers with disjoint lifetimes share storage: the factors of M (until
-    // M^-1 is formed) and P (CZ, then I + T J); the per-dof derivative vectors
-    // and composites (until dtau/dq, dtau/dv are formed) and Q; the FP64 solve
-    // scratch and the columns of the reduced solve.
+    // Buffers with disjoint lifetimes share storage.
+    //  * mx: the factors of M until M^-1 is formed; then (Jacobian) CZ and
+    //    P = I + T J.
+    //  * derivative entries, the union: the FP64 product J M^-1 of the step,
+    //    and beside it G in working precision during the NCP; then the
+    //    per-dof derivative vectors and composites (until dtau/dq, dtau/dv
+    //    and E are formed); then the columns of the reduced solve and the
+    //    transposed-solve vector; then Q = P M^-1.
+    //  * Gd (FP64 G, dead once the reduced system is built) holds Z = A^-1 B,
+    //    then T = -K C Z when it fits.
     const int NN = NV * NV, KK = K * K;
-    const size_t u2 = (size_t(NN > KK ? NN : KK) * sizeof(double));
-    char* mx = reinterpret_cast<char*>(take<double>(p, u2 / sizeof(double), tot));
-    E.Mx = reinterpret_cast<double*>(mx);
+    const size_t SQ = size_t(KN > KK ? KN : KK);  // doubles of the FP64 product / solve columns
+    const bool deriv = entry_has_derivative(entry);
+    {
+        const size_t mxb = size_t(NN) * sizeof(double);
+        const size_t czb = (entry == ENTRY_JAC) ? size_t(KK > NN ? KK : NN) * sizeof(R) : 0;
+        const size_t b = mxb > czb ? mxb : czb;
+        E.Mx = take<double>(p, (b + sizeof(double) - 1) / sizeof(double), tot);
+    }
     E.Mi = take<double>(p, NN, tot);
-    E.scr = take<double>(p, (KN > KK ? KN : KK), tot);
+    double* un = nullptr;
+    if (deriv) {
+        const size_t nvec = size_t(45) * NV + size_t(54) * NB;
+        const size_t gq = (size_t(KK) * sizeof(R) + sizeof(double) - 1) / sizeof(double);
+        size_t u = nvec;
+        if (u < SQ + gq) u = SQ + gq;
+        const size_t qd = (size_t(NN) * sizeof(R) + sizeof(double) - 1) / sizeof(double);
+        if (u < qd) u = qd;
+        un = take<double>(p, u, tot);
+        E.scr = un;
+    } else {
+        E.scr = take<double>(p, SQ, tot);
+    }
     E.mu = take<R>(p, NC, tot);
     E.Winv = take<R>(p, 9 * NC, tot);
     E.J = take<R>(p, K * NV, tot);
     E.KT = take<R>(p, K * NV, tot);
-    E.G = (sizeof(R) == sizeof(double)) ? nullptr : take<R>(p, K * K, tot);
+    if (sizeof(R) == sizeof(double))
+        E.G = nullptr;  // set to Gd below
+    else if (deriv)
+        E.G = reinterpret_cast<R*>(un + SQ);
+    else
+        E.G = take<R>(p, KK, tot);
     E.g = take<R>(p, K, tot);
     E.Lam = take<R>(p, K, tot);
     E.sig = take<R>(p, K, tot);
@@ -252,26 +281,22 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.vrow = take<double>(p, 3 * K, tot);
     E.vcol = take<double>(p, 3 * K, tot);
     E.vdiag = take<double>(p, K, tot);
-    E.Gd = take<double>(p, K * K, tot);
+    E.Gd = take<double>(p, KK, tot);
     if (sizeof(R) == sizeof(double)) E.G = reinterpret_cast<R*>(E.Gd);
     E.gd = take<double>(p, K, tot);
     E.Ld = take<double>(p, K, tot);
     E.Ld1 = take<double>(p, K, tot);
     E.dfr = take<double>(p, 4 * NC, tot);
-    E.A = take<double>(p, K * K, tot);
+    E.A = take<double>(p, KK, tot);
     E.rhs = take<double>(p, K, tot);
     E.X = take<double>(p, K, tot);
     E.ytmp = take<double>(p, K, tot);
     E.dsig = take<double>(p, K, tot);
     E.dsc = take<double>(p, 4, tot);
-    if (entry_has_derivative(entry)) {
+    if (deriv) {
         E.Vp = take<double>(p, 6 * NB, tot);
         E.gint = take<double>(p, NV, tot);
-        // union: {per-dof vectors, composites} | Q
-        const size_t nvec = size_t(45) * NV + size_t(54) * NB;
-        const size_t u1 = nvec * sizeof(double) > size_t(NN) * sizeof(R) ? nvec * sizeof(double) : size_t(NN) * sizeof(R);
-        char* u = reinterpret_cast<char*>(take<double>(p, (u1 + sizeof(double) - 1) / sizeof(double), tot));
-        double* d = reinterpret_cast<double*>(u);
+        double* d = un;
         E.IcS = d; d += 6 * NV;
         E.BtS = d; d += 6 * NV;
         E.EtS = d; d += 3 * NV;
@@ -282,15 +307,18 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.Yv = d; d += 6 * NV;
         E.Bc = d; d += 36 * NB;
         E.Ec = d;
-        E.Q = reinterpret_cast<R*>(u);
-        E.P = reinterpret_cast<R*>(mx);
-        E.Ysc = E.scr;
+        E.Ysc = un;
+        E.Q = reinterpret_cast<R*>(un);
+        E.P = reinterpret_cast<R*>(E.Mx);
         E.dTq = take<R>(p, NN, tot);
         E.dTv = take<R>(p, NN, tot);
         E.E = take<R>(p, K * NV, tot);
-        E.Minv = take<R>(p, NN, tot);
-        E.T = take<R>(p, NV * K, tot);
-        E.Z = take<double>(p, KK, tot);
+        E.Z = E.Gd;
+        if (entry == ENTRY_JAC)
+            E.T = (size_t(NV) * K * sizeof(R) <= size_t(KK) * sizeof(double)) ? reinterpret_cast<R*>(E.Gd)
+                                                                                : take<R>(p, NV * K, tot);
+        else
+            E.T = nullptr;
     }
     return tot;
 }

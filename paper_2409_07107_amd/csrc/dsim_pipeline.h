@@ -320,8 +320,6 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
                       R* dvdtau) {
     const int n = E.nv, k = E.k;
     derivative_partials(T, E, P);
-    // M^-1 (formed in the step) in working precision
-    for (int idx = T.tid; idx < n * n; idx += T.nt) E.Minv[idx] = R(E.Mi[idx]);
     const int m = E.hdr[1];
     R* CZ = E.P;  // k x k, reused before P is formed
     if (m > 0) {
@@ -352,11 +350,12 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
         E.P[idx] = s;
     }
     T.sync();
+    // Q = P M^-1 with the FP64 M^-1 of the step
     for (int idx = T.tid; idx < n * n; idx += T.nt) {
         const int i = idx / n, j = idx - i * n;
-        R s = 0;
-        for (int l = 0; l < n; ++l) s += E.P[i * n + l] * E.Minv[l * n + j];
-        E.Q[idx] = s;
+        double s = 0;
+        for (int l = 0; l < n; ++l) s += double(E.P[i * n + l]) * E.Mi[l * n + j];
+        E.Q[idx] = R(s);
     }
     T.sync();
     const R dt = R(P.dt);

@@ -19,12 +19,13 @@ LIB_PATH = os.path.join(HERE, "libdsim.so")
 F64, F32 = 0, 1
 ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP, ENTRY_STEP_INTEGRATE, ENTRY_STEP_INTEGRATE_VJP = 0, 1, 2, 3, 4
 ST_NCP_NOT_CONVERGED, ST_RANK_DEFICIENT, ST_MODE_DEGENERATE, ST_NONFINITE, ST_POLISH_FAILED = 1, 2, 4, 8, 16
+ST_SIZE_EXCEEDED = 32
 MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
 
 SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim_validate_host",
            "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
-           "dsim_tangent_to_ambient")
+           "dsim_tangent_to_ambient", "dsim_struct_size")
 
 _vp = ctypes.c_void_p
 
@@ -35,7 +36,7 @@ class CBatch(ctypes.Structure):
                 ("body_off", _vp), ("dof_off", _vp), ("cfg_off", _vp), ("contact_off", _vp), ("jac_off", _vp),
                 ("parent", _vp), ("jtype", _vp), ("cbody", _vp),
                 ("axis", _vp), ("jrot", _vp), ("jpos", _vp), ("mass", _vp), ("com", _vp), ("inertia", _vp),
-                ("cpoint", _vp), ("mu", _vp)]
+                ("cpoint", _vp), ("mu", _vp), ("n_order", ctypes.c_int32), ("order", _vp)]
 
 
 class CParams(ctypes.Structure):
@@ -58,6 +59,10 @@ def lib():
         L.dsim_default_params.argtypes = [ctypes.POINTER(CParams), ctypes.c_int32]
         L.dsim_default_params.restype = None
         L.dsim_abi_version.restype = ctypes.c_int32
+        L.dsim_struct_size.argtypes = [ctypes.c_int32]
+        L.dsim_struct_size.restype = ctypes.c_size_t
+        if (L.dsim_struct_size(0), L.dsim_struct_size(1)) != (ctypes.sizeof(CBatch), ctypes.sizeof(CParams)):
+            raise RuntimeError(f"{LIB_PATH} does not match this binding's struct layout: rebuild it")
         L.dsim_error_string.argtypes = [ctypes.c_int32]
         L.dsim_error_string.restype = ctypes.c_char_p
         L.dsim_validate_host.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(ctypes.c_int32)]
@@ -223,7 +228,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
     """v+, impulses, modes and status of one step for every environment."""
     p = p or db.params()
     q = db.q if q is None else q
@@ -231,13 +236,13 @@ def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, ou
     tau = db.tau if tau is None else tau
     out = out or _outputs(db)
     ws, nbytes = db.workspace(p, ENTRY_STEP)
-    _check(lib().dsim_step(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+    _check(lib().dsim_step(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                            _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
                            _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
     return out
 
 
-def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
     """The step plus dv+/d(dq, v, tau), each block n_v x n_v row-major per
     environment, concatenated (offsets: jac_offsets(dof_off))."""
     import torch
@@ -250,7 +255,7 @@ def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None =
         for k in ("dvdq", "dvdv", "dvdtau"):
             out[k] = torch.empty(max(db.n_jac, 1), dtype=db.dtype, device=db.device)
     ws, nbytes = db.workspace(p, ENTRY_JACOBIAN)
-    _check(lib().dsim_step_jacobian(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+    _check(lib().dsim_step_jacobian(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                                     _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                     _ptr(out["status"]), _ptr(out["dvdq"]), _ptr(out["dvdv"]),
                                     _ptr(out["dvdtau"]), _ptr(ws), ctypes.c_size_t(nbytes),
@@ -258,7 +263,7 @@ def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None =
     return out
 
 
-def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
     """The step plus g^T dv+/d(dq, v, tau) for g = g_vnext (per environment)."""
     import torch
     p = p or db.params()
@@ -270,7 +275,7 @@ def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | No
         for k in ("g_q", "g_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
     ws, nbytes = db.workspace(p, ENTRY_VJP)
-    _check(lib().dsim_step_vjp(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+    _check(lib().dsim_step_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                                _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]), _ptr(out["g_tau"]),
                                _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
@@ -285,7 +290,7 @@ def split_jacobian(db: DeviceBatch, out, e: int):
     return np.concatenate(blocks, axis=1)
 
 
-def step_integrate(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None):
+def step_integrate(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
     """The step followed by q+ = q (+) dt v+: adds "q_next" to the step outputs."""
     import torch
     p = p or db.params()
@@ -295,14 +300,14 @@ def step_integrate(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None 
     if out is None:
         out = _outputs(db)
         out["q_next"] = torch.empty_like(q)
-    _check(lib().dsim_step_integrate(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+    _check(lib().dsim_step_integrate(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                                      _ptr(out["q_next"]), _ptr(out["v_next"]), _ptr(out["lam"]),
                                      _ptr(out["mode"]), _ptr(out["status"]), ctypes.c_void_p(_stream())))
     return out
 
 
 def step_integrate_vjp(db: DeviceBatch, a_qnext, a_vnext, q=None, v=None, tau=None, p: CParams | None = None,
-                       out=None):
+                       out=None, cb=None):
     """Adjoint of step_integrate: tangent adjoint a_qnext of q+ and adjoint
     a_vnext of v+ -> "a_q" (tangent), "a_v", "g_tau" (plus the step outputs)."""
     import torch
@@ -314,7 +319,7 @@ def step_integrate_vjp(db: DeviceBatch, a_qnext, a_vnext, q=None, v=None, tau=No
         out = _outputs(db)
         for k in ("a_q", "a_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
-    _check(lib().dsim_step_integrate_vjp(ctypes.byref(db.c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+    _check(lib().dsim_step_integrate_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                                          _ptr(a_qnext), _ptr(a_vnext), _ptr(out["v_next"]), _ptr(out["lam"]),
                                          _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["a_q"]),
                                          _ptr(out["a_v"]), _ptr(out["g_tau"]), ctypes.c_void_p(_stream())))
@@ -329,3 +334,14 @@ def tangent_to_ambient(db: DeviceBatch, q, g_tangent, out=None):
     _check(lib().dsim_tangent_to_ambient(ctypes.byref(db.c), db.precision, _ptr(q), _ptr(g_tangent), _ptr(out),
                                          ctypes.c_void_p(_stream())))
     return out
+
+
+def class_batch(db: DeviceBatch, envs, sizes) -> CBatch:
+    """A CBatch over db's device arrays that launches only the environments
+    listed in `envs` (an int32 device tensor, kept alive by the caller), with
+    buffers sized for `sizes` = (max bodies, max dofs, max cfg, max contacts)."""
+    c = CBatch.from_buffer_copy(db.c)
+    c.max_bodies, c.max_dofs, c.max_cfg, c.max_contacts = (int(x) for x in sizes)
+    c.n_order = int(envs.numel())
+    c.order = envs.data_ptr()
+    return c

@@ -32,6 +32,9 @@ SETS = {
     "arm7_4096_sample": ("arm7", 4096, 0, [0, 1, 2, 63, 64, 1000, 2047, 2048, 3001, 4093, 4094, 4095]),
     "tree36_16384_sample": ("tree36", 16384, 0, [0, 1, 2, 3, 255, 256, 4097, 8191, 8192, 12000,
                                                    16379, 16380, 16381, 16382, 16383]),
+    # ragged trees of 7..40 dof with 0..16 contacts
+    "mixed_8192_sample": ("mixed", 8192, 0, [0, 1, 2, 3, 4, 5, 6, 7, 1000, 2047, 2048, 4095, 4096, 6000,
+                                             8188, 8189, 8190, 8191]),
 }
 
 # rollouts: name -> (workload, n_env, seed, steps, gap_mode, generator options)
@@ -60,8 +63,14 @@ def make(name):
     with Pool(min(8, len(envs))) as p:
         res = p.map(_one, envs)
     out = dict(envs=np.array(envs), workload=wl, n_env=n, seed=seed)
+    ragged = len({r["jac"].shape for r in res}) > 1 or len({r["G"].shape for r in res}) > 1
+    out["ragged"] = ragged
     for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu"):
-        out[key] = np.array([r[key] for r in res], dtype=object if wl == "mixed" else None)
+        if ragged:  # one array per environment (no object arrays in the files)
+            for i, r in enumerate(res):
+                out[f"{key}__{i}"] = np.asarray(r[key])
+        else:
+            out[key] = np.array([r[key] for r in res])
     for key in ("margin", "ok", "unique", "residual"):
         out[key] = np.array([r[key] for r in res])
     path = os.path.join(HERE, f"{name}.npz")

@@ -1,0 +1,139 @@
+"""GPU tests of ragged batches: launch plans (size classes, start order,
+team sizes), the autotuner, graph capture and replay, and parity of the
+mixed-size workload against the oracle's stored results."""
+import numpy as np
+import pytest
+
+from paper_2409_07107_amd import scenes
+from tests.parity_util import TOL, compare, load_golden, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed(n=None, precision=1):
+    from paper_2409_07107_amd import dsim
+    gold = load_golden("mixed_8192_sample")
+    batch = scenes.make("mixed", n or int(gold["n_env"]), seed=int(gold["seed"]))
+    return gold, batch, dsim.DeviceBatch(batch, precision=precision)
+
+
+def _same(a, b, keys):
+    import torch
+    return all(torch.equal(a[k], b[k]) for k in keys)
+
+
+KEYS = ("v_next", "lam", "mode", "status", "dvdq", "dvdv", "dvdtau")
+
+
+def test_mixed_full_size_parity_planned_and_captured(gpu_lib):
+    """The 8192-environment ragged batch, launched as the benchmark does (a
+    three-class plan captured in a graph), against the oracle on sampled
+    environments (FP32 form)."""
+    import torch
+    from paper_2409_07107_amd import autotune, dsim
+    gold, batch, db = _mixed()
+    p = db.params()
+    plan = autotune.make_plan(db, 3, 128, dsim.ENTRY_JACOBIAN)
+    say(f"plan {plan.describe()} lds {autotune.lds_bytes(db, plan, p)}")
+    out = autotune.new_outputs(db, dsim.ENTRY_JACOBIAN)
+    g = autotune.GraphLaunch(db, plan, p, out)
+    g.replay()
+    torch.cuda.synchronize()
+    st = compare(batch, gold, out, db, 1, label="mixed 8192 planned")
+    tol = TOL[1]
+    assert st["included"] >= st["n"] // 3
+    assert st["v_max"] <= tol["v"]
+    assert st["jac_max"] <= tol["jac"]
+    assert st["modes_agree"] == st["included"]
+    assert st["alternatives_invalid"] == 0
+    flagged = int(((out["status"].cpu().numpy() & 17) != 0).sum())
+    say(f"solver flags over the full batch: {flagged} / {batch.n_env}")
+    assert flagged <= batch.n_env // 6
+
+
+def test_planned_launch_equals_one_launch(gpu_lib):
+    """Size classes and the cost order change which buffers and which
+    workgroup compute an environment, not its arithmetic."""
+    import torch
+    from paper_2409_07107_amd import autotune, dsim
+    _, batch, db = _mixed(512)
+    p = db.params()
+    one = dsim.step_jacobian(db, p=p)
+    for n in (2, 4):
+        plan = autotune.make_plan(db, n, 128, dsim.ENTRY_JACOBIAN)
+        out = autotune.run_plan(db, plan, p, autotune.new_outputs(db, dsim.ENTRY_JACOBIAN))
+        torch.cuda.synchronize()
+        assert _same(one, out, KEYS), n
+
+
+def test_graph_replays_match_eager(gpu_lib):
+    """Several replays, with other eager work between them, each reproduce
+    the eager result exactly."""
+    import torch
+    from paper_2409_07107_amd import autotune, dsim
+    _, batch, db = _mixed(256)
+    p = db.params()
+    plan = autotune.make_plan(db, 2, [64, 256], dsim.ENTRY_JACOBIAN)
+    eager = autotune.run_plan(db, plan, p, autotune.new_outputs(db, dsim.ENTRY_JACOBIAN))
+    torch.cuda.synchronize()
+    out = autotune.new_outputs(db, dsim.ENTRY_JACOBIAN)
+    g = autotune.GraphLaunch(db, plan, p, out)
+    for r in range(3):
+        for k in KEYS:
+            out[k].zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert _same(eager, out, KEYS), r
+        dsim.step(db, p=p)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_autotuner_plan_is_valid_and_cached(tmp_path, gpu_lib):
+    import torch
+    from paper_2409_07107_amd import autotune, dsim
+    _, batch, db = _mixed(384)
+    p = db.params()
+    cache = str(tmp_path / "plans.json")
+    plan, table = autotune.autotune(db, p, dsim.ENTRY_JACOBIAN, class_counts=(1, 2, 3), reps=2, cache=cache,
+                                    log=say)
+    assert max(autotune.lds_bytes(db, plan, p)) <= autotune.LDS_LIMIT
+    assert sum(int(c.envs.numel()) for c in plan.classes) == batch.n_env
+    assert any(row["ms"] for row in table)
+    out = autotune.run_plan(db, plan, p, autotune.new_outputs(db, dsim.ENTRY_JACOBIAN))
+    ref = dsim.step_jacobian(db, p=p)
+    torch.cuda.synchronize()
+    ok = (ref["status"] & 17) == 0
+    assert torch.equal(out["mode"], ref["mode"])
+    # team sizes may differ from the single launch: rounding-level changes only
+    for k in ("dvdq", "dvdv", "dvdtau"):
+        assert torch.allclose(out[k], ref[k], rtol=1e-3, atol=1e-5) or not bool(ok.all())
+    plan2, _ = autotune.autotune(db, p, dsim.ENTRY_JACOBIAN, cache=cache)
+    assert plan2.describe() == plan.describe()
+
+
+def test_fp64_form_of_the_largest_class_is_rejected(gpu_lib):
+    """The largest mixed environments need more LDS in the FP64 form than a
+    compute unit has: the call fails with DSIM_ERR_SIZE before any launch."""
+    from paper_2409_07107_amd import dsim
+    _, batch, db = _mixed(64, precision=0)
+    with pytest.raises(dsim.DsimError, match="-2"):
+        dsim.step_jacobian(db)
+
+
+def test_undersized_launch_flags_instead_of_computing(gpu_lib):
+    """A launch whose buffers are smaller than a listed environment skips it
+    and sets DSIM_ST_SIZE_EXCEEDED; invalid list entries are skipped."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    batch = scenes.make("tree36", 4, seed=2)
+    db = dsim.DeviceBatch(batch, precision=1)
+    envs = torch.tensor([0, 1, -1, 99, 3], dtype=torch.int32, device=db.device)
+    nb, nv, nq, nc = batch.max_sizes
+    cb = dsim.class_batch(db, envs, (nb, nv - 1, nq, nc))
+    out = dsim._outputs(db)
+    out["status"].fill_(0)
+    dsim.step(db, out=out, cb=cb)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert all(st[e] == dsim.ST_SIZE_EXCEEDED for e in (0, 1, 3))
+    assert st[2] == 0  # not listed: untouched

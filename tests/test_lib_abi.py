@@ -34,7 +34,10 @@ def test_every_declared_symbol_is_exported(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(dsim.SYMBOLS) <= set(names)
-    assert L.dsim_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "dsim.h")).read()
+    assert L.dsim_abi_version() == int(re.search(r"#define DSIM_ABI_VERSION (\d+)", hdr).group(1))
+    assert L.dsim_struct_size(0) == ctypes.sizeof(dsim.CBatch)
+    assert L.dsim_struct_size(1) == ctypes.sizeof(dsim.CParams)
 
 
 def test_default_params_validate(L):
