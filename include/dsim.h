@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define DSIM_ABI_VERSION 2
+#define DSIM_ABI_VERSION 3
 
 /* return codes */
 #define DSIM_SUCCESS 0
@@ -138,8 +138,8 @@ typedef struct dsim_params {
     double dt;            /* time step (s), > 0 */
     double gravity[3];    /* world gravity (m/s^2) */
     int32_t gap_mode;     /* 0: every contact touches (g = J v_f);
-                             1: g_N += phi/dt with phi = world z of the point
-                             (Appendix D with K_p = K_d = 0) */
+                             1: g_N += phi/dt with phi = world z of the point,
+                             plus the Baumgarte terms of kp, kd (Appendix D) */
     int32_t precision;    /* dsim_precision */
     int32_t ncp_sweeps;   /* block Gauss-Seidel sweeps per round (>= 1) */
     int32_t ncp_rounds;   /* sweep rounds, each followed by Newton refinement */
@@ -148,6 +148,9 @@ typedef struct dsim_params {
     double ncp_tol;       /* relative natural-map residual tolerance */
     double rank_tol;      /* relative pivot tolerance of the reduced factorisation */
     double mode_eps;      /* relative threshold of the mode classification */
+    double kp, kd;        /* Baumgarte gains of Appendix D, used in gap mode 1:
+                             g_N += phi/dt - kp min(phi/dt, 0) - kd (J v)_N;
+                             0 <= kp <= 1, kd >= 0 (defaults 0) */
 } dsim_params;
 
 /* fills `p` with the defaults for `precision` */

@@ -41,7 +41,7 @@ import torch
 
 from . import ncp
 from .rbd import Model, t64, F64
-from .step import forward
+from .step import forward, gap_terms
 
 
 def _modes_system(model: Model, q, modes, gap_mode):
@@ -59,9 +59,8 @@ def _modes_system(model: Model, q, modes, gap_mode):
             return Fdyn
         sig = model.contact_velocity(q, vn, dq)
         if gap_mode == 1:
-            z = model.contact_positions(q, dq)[:, 2]
             add = torch.zeros(3 * nc, dtype=F64)
-            add[2::3] = z / dt
+            add[2::3] = gap_terms(model, q, v, dq)
             sig = sig + add
         rows = []
         for i, md in enumerate(modes):
@@ -128,16 +127,18 @@ def fixed_impulse(env: dict, res: dict):
             return Fdyn
         s = model.contact_velocity(q, vn, dq)
         if model.gap_mode == 1:
-            z = model.contact_positions(q, dq)[:, 2]
             add = torch.zeros(3 * nc, dtype=F64)
-            add[2::3] = z / dt
+            add[2::3] = gap_terms(model, q, v, dq)
             s = s + add
         return torch.cat([Fdyn, s])
 
     th0 = torch.cat([torch.zeros(nv, dtype=F64), t64(env["v"]), t64(env["tau"])])
     Hth = torch.autograd.functional.jacobian(H, th0).numpy()
     D0 = -np.linalg.solve(res["M"], Hth[:nv])
-    E = Hth[nv:, :nv] if nc else np.zeros((0, nv))
+    # the contact-velocity rows' own dependence on theta at fixed v+: the q
+    # columns are E = d(J v+)/dq (+ gap terms); the Baumgarte damping term
+    # also depends on v
+    E = Hth[nv:] if nc else np.zeros((0, 3 * nv))
     return D0, E
 
 
@@ -149,8 +150,7 @@ def appendix_b(env: dict, res: dict | None = None):
     G, Lam, sig, J = res["G"], res["Lam"], res["sigma"], res["J"]
     modes = res["modes"]
     D0, E = fixed_impulse(env, res)
-    rhs = J @ D0
-    rhs[:, :nv] += E
+    rhs = J @ D0 + E
     stk = [i for i in range(nc) if modes[i] == ncp.STK]
     sld = [i for i in range(nc) if modes[i] == ncp.SLD]
     m = 3 * len(stk) + 2 * len(sld)

@@ -140,6 +140,8 @@ class Model:
         self.dt = float(env["dt"])
         self.gravity = t64(env["gravity"]).reshape(3)
         self.gap_mode = int(env["gap_mode"])
+        self.kp = float(env.get("kp", 0.0))
+        self.kd = float(env.get("kd", 0.0))
         # coordinate bookkeeping
         self.dof0, self.cfg0, self.ndof = [], [], []
         nv = nq = 0

@@ -54,6 +54,8 @@ Params params_of(const dsim_params* p) {
     q.ncp_tol = p->ncp_tol;
     q.rank_tol = p->rank_tol;
     q.mode_eps = p->mode_eps;
+    q.kp = p->kp;
+    q.kd = p->kd;
     return q;
 }
 
@@ -258,6 +260,7 @@ int32_t dsim_validate_params(const dsim_params* p) {
     if (p->ncp_sweeps < 1 || p->ncp_rounds < 1 || p->newton_iters < 0) return DSIM_ERR_ARG;
     if (p->threads != 0 && p->threads != 64 && p->threads != 128 && p->threads != 256) return DSIM_ERR_ARG;
     if (!(p->ncp_tol > 0) || !(p->rank_tol > 0) || !(p->mode_eps >= 0)) return DSIM_ERR_ARG;
+    if (!(p->kp >= 0 && p->kp <= 1) || !(p->kd >= 0) || !std::isfinite(p->kd)) return DSIM_ERR_ARG;
     return DSIM_SUCCESS;
 }
 

@@ -78,6 +78,7 @@ struct Params {
     double dt, gx, gy, gz;
     int gap_mode, ncp_sweeps, ncp_rounds, newton_iters;
     double ncp_tol, rank_tol, mode_eps;
+    double kp, kd;  // Baumgarte gains (gap mode 1)
 };
 
 struct Dims {

@@ -261,7 +261,31 @@ DSIM_HD void velocity_partials(const Team& T, Env<R>& E, const Params& P) {
             cross3(Sj, du, t1);
             cross3(wl, dx, t2);
             val = t1[r] + t2[r];
-            if (P.gap_mode == 1 && r == 2) val += dx[2] / P.dt;
+            if (P.gap_mode == 1 && r == 2) {
+                // d/dq of phi/dt - kp [phi/dt]_- (slope 0 at phi = 0) ...
+                const double phi = x[2] + E.org[2];
+                val += (1.0 - (phi < 0 ? P.kp : 0.0)) * dx[2] / P.dt;
+                // ... and of -kd (J(q) v)_N at fixed v (E.V: body velocities at v)
+                if (P.kd != 0.0) {
+                    double vi[3], vl[3] = {0, 0, 0}, w0[3] = {0, 0, 0};
+                    const double* Wi = E.V + 6 * b;
+                    cross3(Wi, x, vi);
+                    for (int a = 0; a < 3; ++a) vi[a] += Wi[3 + a];
+                    if (par >= 0) {
+                        const double* Wl = E.V + 6 * par;
+                        cross3(Wl, x, vl);
+                        for (int a = 0; a < 3; ++a) {
+                            vl[a] += Wl[3 + a];
+                            w0[a] = Wl[a];
+                        }
+                    }
+                    const double dv[3] = {vi[0] - vl[0], vi[1] - vl[1], vi[2] - vl[2]};
+                    double s1[3], s2[3];
+                    cross3(Sj, dv, s1);
+                    cross3(w0, dx, s2);
+                    val -= P.kd * (s1[2] + s2[2]);
+                }
+            }
         }
         E.E[idx] = R(val);
     }
@@ -369,8 +393,13 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
             sv += ql * E.dTv[l * n + j];
         }
         for (int r = 0; r < k; ++r) se += E.T[i * k + r] * E.E[r * n + j];
+        // Baumgarte damping: the normal rows of the contact equation also
+        // depend on v through -kd J_N v (Appendix D)
+        R sd = 0;
+        if (P.gap_mode == 1 && P.kd != 0.0)
+            for (int r = 2; r < k; r += 3) sd += E.T[i * k + r] * E.J[r * n + j];
         dvdq[off + idx] = -dt * sq + se;
-        dvdv[off + idx] = E.P[idx] - dt * sv;
+        dvdv[off + idx] = E.P[idx] - dt * sv - R(P.kd) * sd;
         dvdtau[off + idx] = dt * E.Q[idx];
     }
     T.sync();
@@ -583,8 +612,11 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
             sv += double(E.dTv[l * n + j]) * pg[l];
         }
         for (int r = 0; r < k; ++r) se += double(E.E[r * n + j]) * tg[r];
+        double sd = 0;  // Baumgarte damping (Appendix D): -kd J_N^T tg
+        if (P.gap_mode == 1 && P.kd != 0.0)
+            for (int r = 2; r < k; r += 3) sd += double(E.J[r * n + j]) * tg[r];
         gq[E.d0 + j] = R(-P.dt * sq + se + (aqn ? E.gint[j] : 0.0));
-        gv[E.d0 + j] = R(pk[j] - P.dt * sv);
+        gv[E.d0 + j] = R(pk[j] - P.dt * sv - P.kd * sd);
         gtau[E.d0 + j] = R(P.dt * pg[j]);
     }
     T.sync();

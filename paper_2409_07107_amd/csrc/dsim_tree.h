@@ -423,7 +423,13 @@ DSIM_HD void delassus(const Team& T, Env<R>& E, const Params& P) {
         double s = 0;
         const R* x = E.J + r * n;
         for (int i = 0; i < n; ++i) s += double(x[i]) * E.vf[i];
-        if (P.gap_mode == 1 && (r % 3) == 2) s += (E.xw[r] + E.org[2]) / P.dt;
+        if (P.gap_mode == 1 && (r % 3) == 2) {
+            // Baumgarte form (Appendix D): phi/dt - kp [phi/dt]_- - kd (J v)_N
+            const double z = (E.xw[r] + E.org[2]) / P.dt;
+            double jv = 0;
+            for (int i = 0; i < n; ++i) jv += double(x[i]) * E.v[i];
+            s += z - P.kp * (z < 0 ? z : 0.0) - P.kd * jv;
+        }
         E.gd[r] = s;
         E.g[r] = R(s);
     }

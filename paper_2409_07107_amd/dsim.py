@@ -43,7 +43,8 @@ class CParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("gap_mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("ncp_sweeps", ctypes.c_int32), ("ncp_rounds", ctypes.c_int32),
                 ("newton_iters", ctypes.c_int32), ("threads", ctypes.c_int32), ("ncp_tol", ctypes.c_double),
-                ("rank_tol", ctypes.c_double), ("mode_eps", ctypes.c_double)]
+                ("rank_tol", ctypes.c_double), ("mode_eps", ctypes.c_double), ("kp", ctypes.c_double),
+                ("kd", ctypes.c_double)]
 
 
 _LIB = None
@@ -194,6 +195,8 @@ class DeviceBatch:
         for i in range(3):
             p.gravity[i] = float(g[i])
         p.gap_mode = int(overrides.get("gap_mode", self.batch.gap_mode))
+        p.kp = float(overrides.get("kp", getattr(self.batch, "kp", 0.0)))
+        p.kd = float(overrides.get("kd", getattr(self.batch, "kd", 0.0)))
         return p
 
     def workspace(self, p: CParams, entry: int):

@@ -65,6 +65,8 @@ class Batch:
     dt: float = 1e-3
     gravity: tuple = GRAVITY
     gap_mode: int = 0          # 0: every listed contact touches; 1: gap phi = z/dt
+    kp: float = 0.0            # Baumgarte gains (gap mode 1 only)
+    kd: float = 0.0
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -81,7 +83,7 @@ class Batch:
             cbody=self.cbody[c0:c1], cpoint=self.cpoint[c0:c1], mu=self.mu[c0:c1],
             q=self.q[q0:q1], v=self.v[d0:d1], tau=self.tau[d0:d1],
             dt=self.dt, gravity=np.asarray(self.gravity, dtype=np.float64),
-            gap_mode=self.gap_mode,
+            gap_mode=self.gap_mode, kp=self.kp, kd=self.kd,
         )
 
     def sizes(self, e: int):

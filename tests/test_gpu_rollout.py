@@ -204,20 +204,21 @@ def test_checkpointing_does_not_change_the_gradient(gpu_lib):
 
 def test_long_rollout_directional_derivative(gpu_lib):
     """Property at rollout length: the FP64 gradient agrees with central
-    differences of the FP64 forward rollout along a random torque direction
-    (environments whose solver flagged any step are skipped)."""
+    differences of the FP64 forward rollout along a random torque direction,
+    on the environments whose solver flagged no step of the three rollouts
+    and whose stencil crossed no mode switch (differences are then smooth)."""
     import torch
     from paper_2409_07107_amd import rollout
-    batch = scenes.make("tree36", 16, seed=6)
+    batch = scenes.make("tree36", 48, seed=6)
     db = _db(batch, 0)
-    T = 40
+    T = 20
     rng = np.random.default_rng(8)
     tt = torch.as_tensor(rng.normal(scale=0.3, size=(T, db.n_dof)), dtype=db.dtype, device=db.device)
     d = torch.as_tensor(rng.normal(size=(T, db.n_dof)), dtype=db.dtype, device=db.device)
     targets = np.stack([batch.q[batch.cfg_off[e]:batch.cfg_off[e] + 3] + 0.1 for e in range(batch.n_env)])
     lf = rollout.base_position_loss(db, targets)
-    loss, grad, info = rollout.rollout_gradient(db, db.q, db.v, tt, lf, checkpoint=20)
-    h = 1e-5
+    loss, grad, info = rollout.rollout_gradient(db, db.q, db.v, tt, lf, checkpoint=7)
+    h = 1e-7
     qp, vp, sp = rollout.rollout(db, db.q, db.v, tt + h * d)
     qm, vm, sm = rollout.rollout(db, db.q, db.v, tt - h * d)
     lp, lm = lf(qp, vp)[0], lf(qm, vm)[0]
@@ -225,16 +226,16 @@ def test_long_rollout_directional_derivative(gpu_lib):
     fd = ((lp - lm) / (2 * h)).cpu().numpy()
     gd = (grad * d).cpu().numpy()
     bad = (info["status"] | sp | sm).cpu().numpy() & 17
-    n = 0
+    clean = agree = 0
     for e in range(batch.n_env):
         if bad[e]:
             continue
+        clean += 1
         d0, d1 = batch.dof_off[e], batch.dof_off[e + 1]
         an = gd[:, d0:d1].sum()
-        if abs(fd[e] - an) > 1e-5 * max(abs(an), 1e-9):
-            say(f"env {e}: fd {fd[e]:.6e} analytic {an:.6e}")
+        if abs(fd[e] - an) <= 1e-4 * max(abs(an), 1e-9):
+            agree += 1
         else:
-            n += 1
-    say(f"directional derivative agrees on {n} of {batch.n_env} environments")
-    # a mode switch inside the stencil spoils a few; most must agree
-    assert n >= batch.n_env // 2
+            say(f"env {e}: fd {fd[e]:.6e} analytic {an:.6e}")
+    say(f"directional derivative agrees on {agree} of {clean} unflagged environments ({batch.n_env} in all)")
+    assert agree >= 4 and agree >= 0.7 * clean

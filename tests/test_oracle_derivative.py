@@ -161,9 +161,16 @@ def test_ift_equals_appendix_b(name, n):
     assert compared >= 1
 
 
-@pytest.mark.parametrize("name,seed", [("arm7", 31), ("arm7", 32), ("cube", 33)])
-def test_ift_matches_central_differences(name, seed):
+@pytest.mark.parametrize("name,seed,gap", [("arm7", 31, None), ("arm7", 32, None), ("cube", 33, None),
+                                           ("arm7", 34, (0.3, 0.2)), ("cube", 35, (0.4, 0.3))])
+def test_ift_matches_central_differences(name, seed, gap):
+    """gap = (K_p, K_d): gap mode 1 with Baumgarte terms (Appendix D)."""
     bt = scenes.make(name, 4, seed=seed)
+    if gap is not None:
+        bt.gap_mode, (bt.kp, bt.kd) = 1, gap
+        if name == "cube":  # press the cubes slightly into the plane
+            for e in range(bt.n_env):
+                bt.q[bt.cfg_off[e] + 2] -= 1e-4
     checked = 0
     for e in range(bt.n_env):
         env = bt.env(e)
@@ -179,3 +186,25 @@ def test_ift_matches_central_differences(name, seed):
         assert err <= 1e-6 * max(1.0, np.abs(d["jac"]).max()), err
         checked += 1
     assert checked >= 1
+
+
+@pytest.mark.parametrize("kp,kd", [(0.0, 0.0), (0.5, 0.3), (1.0, 0.8)])
+def test_baumgarte_derivative_matches_central_differences(kp, kd):
+    """Gap mode 1 with the Baumgarte terms of Appendix D: single off-centre
+    contacts pressed into, resting on or leaving the plane, in every mode."""
+    from tests.gap_scenes import pressed_bodies
+    bt = pressed_bodies(12, 4, kp, kd)
+    checked = 0
+    for e in range(bt.n_env):
+        env = bt.env(e)
+        r = forward(env)
+        if r["margin"] < 1e-3:
+            continue
+        d = derivative.ift(env, r)
+        # the proportional term's 1/dt scaling makes the q columns large:
+        # a smaller step keeps the truncation error below the tolerance
+        fd, valid = derivative.finite_differences(env, r, h=1e-7)
+        err = np.abs(fd[:, valid] - d["jac"][:, valid]).max()
+        assert err <= 1e-6 * max(1.0, np.abs(d["jac"]).max()), (e, err)
+        checked += 1
+    assert checked >= 8

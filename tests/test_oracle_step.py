@@ -92,3 +92,32 @@ def test_workload_solutions_satisfy_ncp(name):
         r = forward(bt.env(e))
         assert r["info"]["ok"]
         assert ncp.check(r["G"], r["g"], r["model"].mu, r["Lam"], tol=1e-10)
+
+
+@pytest.mark.parametrize("kp,kd,depth", [(0.0, 0.0, 2e-4), (0.3, 0.0, 2e-4), (0.3, 0.4, 2e-4), (0.5, 0.2, -1e-5)])
+def test_baumgarte_normal_velocity_of_a_pressed_cube(kp, kd, depth):
+    """Appendix D: for touching (sticking or sliding) contacts the normal
+    velocity after the step is K_d (J v)_N - (1 - K_p [phi < 0]) phi / dt.
+    A flat, non-rotating cube pushed down at depth d (phi = -d on all four
+    corners) with a downward velocity sticks and lifts at exactly that rate."""
+    b = scenes.cube(1, seed=0, v_std=0.0)
+    b.gap_mode, b.kp, b.kd = 1, kp, kd
+    env = b.env(0)
+    env["q"] = np.array(env["q"], dtype=np.float64)
+    env["q"][2] -= depth
+    vz = -0.02
+    env["v"] = np.array([0.0, 0.0, vz, 0.0, 0.0, 0.0])
+    r = forward(env)
+    phi = -depth
+    if phi < 0:
+        assert r["modes"] == [ncp.STK] * 4
+        expect = kd * vz - (1.0 - kp) * phi / DT
+        assert abs(r["vnext"][2] - expect) < 1e-12
+        assert np.abs(r["vnext"][[0, 1, 3, 4, 5]]).max() < 1e-12
+    else:
+        # above the plane by 1e-5 m: free fall does not reach it in one step
+        # once the damping term is counted, so the contacts break
+        vf = vz + DT * GZ
+        if vf + phi / DT - kd * vz >= 0:
+            assert r["modes"] == [ncp.BRK] * 4
+            assert abs(r["vnext"][2] - vf) < 1e-12
