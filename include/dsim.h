@@ -176,9 +176,13 @@ int32_t dsim_validate_host(const dsim_batch* host_batch, int32_t* bad_env);
 /* Checks of the parameter block alone (host). */
 int32_t dsim_validate_params(const dsim_params* params);
 
-/* Bytes of device workspace the given entry needs for this batch.  Every
- * entry keeps its working set on chip, so this is 0 and the `ws` arguments
- * may be NULL; they are kept for ABI stability. */
+/* Bytes of device workspace the given entry needs for this batch: 0 for the
+ * step entries, n_env * 504 for the derivative entries (Jacobian, VJP and
+ * the rollout adjoint), which run as two launches on `stream` -- the step,
+ * then the derivative -- and hand the FP64 contact impulses of each
+ * environment from the first to the second through the workspace.  Every
+ * other quantity stays on chip.  The workspace is the caller's; it must not
+ * be shared by calls that may run concurrently. */
 size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
 
 /* Bytes of on-chip (LDS) storage one environment team uses for `entry`
@@ -247,7 +251,8 @@ int32_t dsim_step_integrate_vjp(const dsim_batch* batch, const dsim_params* para
                                 const void* q, const void* v, const void* tau,
                                 const void* a_qnext, const void* a_vnext,
                                 void* v_next, void* lam, int8_t* mode, int32_t* status,
-                                void* a_q, void* a_v, void* g_tau, void* stream);
+                                void* a_q, void* a_v, void* g_tau,
+                                void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Maps a gradient in the tangent coordinates of q (g_tangent [sum n_v], as

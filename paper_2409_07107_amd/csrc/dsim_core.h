@@ -61,6 +61,10 @@ enum { BRK = 0, STK = 1, SLD = 2 };
 // entries: the step; the step and its full Jacobian; the step and its VJP;
 // the step followed by q+ = q (+) dt v+; the adjoint of that fused map
 enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4 };
+// FP64 impulses handed from the step launch to the derivative launch: one
+// slot of 3 x (maximum contacts) per environment
+constexpr int kLdStride = 63;
+
 DSIM_HD inline bool entry_has_derivative(int entry) {
     return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP;
 }
@@ -242,17 +246,25 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     //    transposed-solve vector; then Q = P M^-1.
     //  * Gd (FP64 G, dead once the reduced system is built) holds Z = A^-1 B,
     //    then T = -K C Z when it fits.
+    //  * step-only entries: the factors of M, then the FP64 product J M^-1;
+    //    M^-1 (dead once J M^-1 is formed), then Gd and A.
     const int NN = NV * NV, KK = K * K;
     const size_t SQ = size_t(KN > KK ? KN : KK);  // doubles of the FP64 product / solve columns
     const bool deriv = entry_has_derivative(entry);
-    {
+    double* un = nullptr;
+    double* gda = nullptr;
+    if (!deriv) {
+        E.Mx = take<double>(p, size_t(NN > KN ? NN : KN), tot);
+        E.scr = E.Mx;
+        gda = take<double>(p, size_t(NN > 2 * KK ? NN : 2 * KK), tot);
+        E.Mi = gda;
+    } else {
         const size_t mxb = size_t(NN) * sizeof(double);
         const size_t czb = (entry == ENTRY_JAC) ? size_t(KK > NN ? KK : NN) * sizeof(R) : 0;
         const size_t b = mxb > czb ? mxb : czb;
         E.Mx = take<double>(p, (b + sizeof(double) - 1) / sizeof(double), tot);
+        E.Mi = take<double>(p, NN, tot);
     }
-    E.Mi = take<double>(p, NN, tot);
-    double* un = nullptr;
     if (deriv) {
         const size_t nvec = size_t(45) * NV + size_t(54) * NB;
         const size_t gq = (size_t(KK) * sizeof(R) + sizeof(double) - 1) / sizeof(double);
@@ -262,8 +274,6 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         if (u < qd) u = qd;
         un = take<double>(p, u, tot);
         E.scr = un;
-    } else {
-        E.scr = take<double>(p, SQ, tot);
     }
     E.mu = take<R>(p, NC, tot);
     E.Winv = take<R>(p, 9 * NC, tot);
@@ -282,13 +292,13 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.vrow = take<double>(p, 3 * K, tot);
     E.vcol = take<double>(p, 3 * K, tot);
     E.vdiag = take<double>(p, K, tot);
-    E.Gd = take<double>(p, KK, tot);
+    E.Gd = gda ? gda : take<double>(p, KK, tot);
     if (sizeof(R) == sizeof(double)) E.G = reinterpret_cast<R*>(E.Gd);
     E.gd = take<double>(p, K, tot);
     E.Ld = take<double>(p, K, tot);
     E.Ld1 = take<double>(p, K, tot);
     E.dfr = take<double>(p, 4 * NC, tot);
-    E.A = take<double>(p, KK, tot);
+    E.A = gda ? gda + KK : take<double>(p, KK, tot);
     E.rhs = take<double>(p, K, tot);
     E.X = take<double>(p, K, tot);
     E.ytmp = take<double>(p, K, tot);

@@ -42,6 +42,56 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
     residual_and_flags(T, E, P);
 }
 
+// The step's quantities for the derivative, recomputed from (q, v, tau) with
+// the NCP solution and modes of an earlier step launch: kinematics,
+// dynamics, factorisation, contact rows, then the reduced system at that
+// solution (what the step launch computed, without the solve).
+template <class R>
+DSIM_HD void restore_step(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
+                          const double* ld, const int8_t* mode) {
+    kinematics(T, E, B, q);
+    mass_matrix(T, E);
+    rnea(T, E, P, nullptr, 0.0, E.bias);
+    ltdl(T, E);
+    tree_inverse(T, E);
+    for (int i = T.tid; i < E.nv; i += T.nt) {
+        double s = 0;
+        for (int j = 0; j < E.nv; ++j) s += E.Mi[i * E.nv + j] * (E.tau[j] - E.bias[j]);
+        E.af[i] = s;
+        E.vf[i] = E.v[i] + P.dt * s;
+    }
+    T.sync();
+    const int n = E.nv, k = E.k;
+    if (k > 0) {
+        contact_jacobian(T, E);
+        delassus(T, E, P);
+    }
+    const double* l = ld + size_t(E.e) * kLdStride;
+    for (int r = T.tid; r < k; r += T.nt) {
+        E.Ld[r] = l[r];
+        E.Lam[r] = R(l[r]);
+    }
+    for (int c = T.tid; c < E.nc; c += T.nt) E.cmode[c] = mode[E.c0 + c];
+    T.sync();
+    if (k > 0) {
+        fp64_sigma(T, E);
+        reduced_vars(T, E);
+        build_A(T, E);
+        factor_A(T, E, P.rank_tol);
+    } else if (T.tid == 0) {
+        E.hdr[1] = 0;
+        E.hdr[4] = 0;
+    }
+    T.sync();
+    for (int i = T.tid; i < n; i += T.nt) {
+        double s = 0;
+        for (int c = 0; c < k; ++c) s += double(E.KT[c * n + i]) * E.Ld[c];
+        E.vn[i] = E.vf[i] + s;
+        E.ap[i] = E.af[i] + s / P.dt;
+    }
+    T.sync();
+}
+
 template <class R>
 DSIM_HD void write_step(const Team& T, Env<R>& E, R* v_next, R* lam, int8_t* mode, int32_t* status) {
     bool bad = false;
@@ -623,17 +673,30 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
 }
 
 // Full pipeline of one environment.
+//
+// The step entries (STEP, SINT) solve the step and write its outputs, and
+// the FP64 impulses to `ld` when given.  The derivative entries (JAC, VJP,
+// RVJP) run after a step launch over the same environments: they restore
+// the step from `ld` and the written modes, then differentiate it.
 template <class R>
 DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, int entry, int e,
                      const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
-                     int8_t* mode, int32_t* status, R* o1, R* o2, R* o3) {
+                     int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, double* ld) {
     load_env(T, E, B, e, q, v, tau);
-    step_forward(T, E, B, P, q);
-    write_step(T, E, v_next, lam, mode, status);
-    if (entry == ENTRY_JAC) jacobian(T, E, B, P, o1, o2, o3);
-    if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
-    if (entry == ENTRY_SINT) integrate(T, E, P, q, o1);
-    if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
+    if (!entry_has_derivative(entry)) {
+        step_forward(T, E, B, P, q);
+        write_step(T, E, v_next, lam, mode, status);
+        if (ld) {
+            double* l = ld + size_t(E.e) * kLdStride;
+            for (int r = T.tid; r < E.k; r += T.nt) l[r] = E.Ld[r];
+        }
+        if (entry == ENTRY_SINT) integrate(T, E, P, q, o1);
+    } else {
+        restore_step(T, E, B, P, q, ld, mode);
+        if (entry == ENTRY_JAC) jacobian(T, E, B, P, o1, o2, o3);
+        if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
+        if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
+    }
     T.sync();
 }
 

@@ -84,7 +84,7 @@ def lib():
         L.dsim_step_integrate.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + [_vp]
         L.dsim_step_integrate.restype = ctypes.c_int32
         L.dsim_step_integrate_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
-            [_vp]
+            [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_integrate_vjp.restype = ctypes.c_int32
         L.dsim_tangent_to_ambient.argtypes = [ctypes.POINTER(CBatch), ctypes.c_int32, _vp, _vp, _vp, _vp]
         L.dsim_tangent_to_ambient.restype = ctypes.c_int32
@@ -322,10 +322,12 @@ def step_integrate_vjp(db: DeviceBatch, a_qnext, a_vnext, q=None, v=None, tau=No
         out = _outputs(db)
         for k in ("a_q", "a_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
-    _check(lib().dsim_step_integrate_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
-                                         _ptr(a_qnext), _ptr(a_vnext), _ptr(out["v_next"]), _ptr(out["lam"]),
-                                         _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["a_q"]),
-                                         _ptr(out["a_v"]), _ptr(out["g_tau"]), ctypes.c_void_p(_stream())))
+    ws, nbytes = db.workspace(p, ENTRY_STEP_INTEGRATE_VJP)
+    _check(lib().dsim_step_integrate_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q),
+                                         _ptr(v), _ptr(tau), _ptr(a_qnext), _ptr(a_vnext), _ptr(out["v_next"]),
+                                         _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
+                                         _ptr(out["a_q"]), _ptr(out["a_v"]), _ptr(out["g_tau"]), _ptr(ws),
+                                         ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
     return out
 
 
