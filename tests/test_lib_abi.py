@@ -46,7 +46,8 @@ def test_default_params_validate(L):
         p = dsim.params(prec)
         assert L.dsim_validate_params(ctypes.byref(p)) == 0
     bad = [dict(dt=0.0), dict(dt=float("nan")), dict(gap_mode=2), dict(precision=5), dict(ncp_sweeps=0),
-           dict(threads=96), dict(ncp_tol=0.0), dict(rank_tol=-1.0)]
+           dict(threads=96), dict(ncp_tol=0.0), dict(rank_tol=-1.0), dict(kp=1.5), dict(kp=-0.1),
+           dict(kd=-1.0), dict(kd=float("inf"))]
     for b in bad:
         p = dsim.params(dsim.F32, **b)
         assert L.dsim_validate_params(ctypes.byref(p)) == -1, b
@@ -125,7 +126,15 @@ def test_on_chip_sizing(L):
     cb = dsim._host_batch_struct(b, keep)
     for prec in (dsim.F32, dsim.F64):
         p = dsim.params(prec)
-        lds = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), 1)
+        lds = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_JACOBIAN)
         assert 0 < lds <= 160 * 1024
-        assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), 1) == 0
-        assert L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), 0) < lds
+        # the step of a 36-dof tree with 8 contacts leaves room for two or
+        # three teams on one compute unit
+        step = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_STEP)
+        assert step <= 160 * 1024 // (3 if prec == dsim.F32 else 2)
+        # the derivative entries hand 63 FP64 impulses per environment over
+        # from their step launch; the step entries need no workspace
+        for entry in (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP, dsim.ENTRY_STEP_INTEGRATE_VJP):
+            assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 504 * b.n_env
+        for entry in (dsim.ENTRY_STEP, dsim.ENTRY_STEP_INTEGRATE):
+            assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 0
