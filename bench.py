@@ -32,7 +32,8 @@ if ROOT not in sys.path:
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 WORKLOAD = dict(name="tree36", n_env=16384, seed=0)
 KERNEL = "env_kernel<float, jacobian>"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "env_kernel_f32_jacobian_tree36_16384_traffic.json")
+STEP_KERNEL = "env_kernel<float, step>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "env_kernel_f32_step_tree36_16384_traffic.json")
 
 
 def measured_traffic():
@@ -50,15 +51,19 @@ def measured_traffic():
 
 
 def algorithmic_flops(batch, modes, sweeps):
-    """Per-environment algorithmic FLOP counts of the step + full Jacobian,
-    using the tree sparsity (not dense n^3): returns (fp32_like, fp64) summed
-    over the batch.  Terms (one FMA = 2 flops): kinematics and dynamics
-    400 per body; factorisation sum d_i^2; Delassus 4 nnzL k + k (k+1) n;
-    NCP sweeps s (2 k^2 + 50 n_c) + 4 nnzL (n_c + 1); partial derivatives of
-    inverse dynamics 150 nnzL; fixed-impulse derivative 4 nnzL p;
-    right-hand side 2 nnzJ p + 6 k; assembly 2 nnzJ p + 4 nnzL p; FP64
-    factorisation m^3/3 + 2/3 (2 n_sld)^3 and solve 2 m^2 p, with p = 3 n."""
-    f32 = f64 = 0.0
+    """Per-environment algorithmic FLOP counts, using the tree sparsity (not
+    dense n^3), summed over the batch and split by launch: returns
+    (step, derivative, fp64) with the FP64 reduced factorisation and solve
+    counted separately (one FMA = 2 flops).
+    Step launch: kinematics and dynamics 400 per body; factorisation
+    sum d_i^2; Delassus 4 nnzL k + k (k+1) n; contact sweeps
+    s (2 k^2 + 50 n_c) + 4 nnzL (n_c + 1).
+    Derivative launch: the same tree and Delassus work again (it restores the
+    step), partial derivatives of inverse dynamics 150 nnzL, fixed-impulse
+    derivative 4 nnzL p, right-hand side 2 nnzJ p + 6 k, assembly
+    2 nnzJ p + 4 nnzL p, and in FP64 the factorisation m^3/3 + 2/3 (2 n_sld)^3
+    and solve 2 m^2 p, with p = 3 n."""
+    fs = fd = f64 = 0.0
     for e in range(batch.n_env):
         b0, b1 = batch.body_off[e], batch.body_off[e + 1]
         c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
@@ -83,11 +88,11 @@ def algorithmic_flops(batch, modes, sweeps):
         nstk, nsld = float((md == 1).sum()), float((md == 2).sum())
         m = 3 * nstk + 2 * nsld
         p = 3 * n
-        f32 += (400 * nb + (d * d).sum() + 4 * nnzL * k + k * (k + 1) * n
-                + sweeps * (2 * k * k + 50 * nc) + 4 * nnzL * (nc + 1)
-                + 150 * nnzL + 4 * nnzL * p + 2 * nnzJ * p + 6 * k + 2 * nnzJ * p + 4 * nnzL * p)
+        tree = 400 * nb + (d * d).sum() + 4 * nnzL * k + k * (k + 1) * n
+        fs += tree + sweeps * (2 * k * k + 50 * nc) + 4 * nnzL * (nc + 1)
+        fd += tree + 150 * nnzL + 4 * nnzL * p + 2 * nnzJ * p + 6 * k + 2 * nnzJ * p + 4 * nnzL * p
         f64 += m ** 3 / 3 + (2.0 / 3.0) * (2 * nsld) ** 3 + 2 * m * m * p
-    return f32, f64
+    return fs, fd, f64
 
 
 def _oracle_init():
@@ -148,20 +153,36 @@ def run(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+        # the step launch alone (the first of the entry's two launches)
+        so = dsim.step(db, p=p)
+        for i in range(steps):
+            starts[i].record()
+            dsim.step(db, p=p, out=so)
+            ends[i].record()
+        torch.cuda.synchronize()
+        step_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
         status = out["status"].cpu().numpy()
         modes = out["mode"].cpu().numpy()
-        results[prec] = dict(wall=wall, steps=steps, kern_ms=kern_ms, status=status, modes=modes,
-                             lds=db.lds_bytes(p, dsim.ENTRY_JACOBIAN), sweeps=p.ncp_sweeps)
+        results[prec] = dict(wall=wall, steps=steps, kern_ms=kern_ms, step_ms=step_ms, status=status, modes=modes,
+                             lds=db.lds_bytes(p, dsim.ENTRY_JACOBIAN), lds_step=db.lds_bytes(p, dsim.ENTRY_STEP),
+                             sweeps=p.ncp_sweeps)
         print(f"[bench] precision {prec}: {steps} steps, {wall / steps * 1e3:.3f} ms/step, "
-              f"kernel {kern_ms:.3f} ms, flagged {int(((status & 17) != 0).sum())}", file=sys.stderr, flush=True)
+              f"launches {kern_ms:.3f} ms (step {step_ms:.3f} ms), flagged {int(((status & 17) != 0).sum())}",
+              file=sys.stderr, flush=True)
     if args.only_f32:
         return
     r32, r64 = results[dsim.F32], results[dsim.F64]
     n = batch.n_env
     value = n * r32["steps"] / r32["wall"]
     fp64_value = n * r64["steps"] / r64["wall"]
-    f32, f64 = algorithmic_flops(batch, r32["modes"], r32["sweeps"])
-    achieved = (f32 + f64) / (r32["kern_ms"] * 1e-3) / 1e12
+    fs, fd, f64 = algorithmic_flops(batch, r32["modes"], r32["sweeps"])
+    deriv_ms = r32["kern_ms"] - r32["step_ms"]
+    kernels = [dict(kernel=STEP_KERNEL, ms=r32["step_ms"], algorithmic_flops=fs, lds_bytes=r32["lds_step"],
+                    tflops=fs / (r32["step_ms"] * 1e-3) / 1e12),
+               dict(kernel=KERNEL, ms=deriv_ms, algorithmic_flops=fd + f64, lds_bytes=r32["lds"],
+                    tflops=(fd + f64) / (deriv_ms * 1e-3) / 1e12)]
+    dom = max(kernels, key=lambda x: x["ms"])
+    achieved = dom["tflops"]
     traffic = measured_traffic()
     cores = int(os.environ.get("BENCH_CPU_CORES", min(16, os.cpu_count() or 1)))
     cpu = None if args.no_cpu else cpu_baseline(batch, cores)
@@ -178,9 +199,11 @@ def run(args):
                        "ms_per_step": r64["wall"] / r64["steps"] * 1e3, "fp32_over_fp64": value / fp64_value},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
-                     "kernel": KERNEL, "kernel_ms": r32["kern_ms"],
-                     "algorithmic_flops_per_launch": f32 + f64, "fp64_flops_per_launch": f64,
-                     "lds_bytes_per_team": r32["lds"]},
+                     "kernel": dom["kernel"], "kernel_ms": dom["ms"],
+                     "algorithmic_flops_per_launch": dom["algorithmic_flops"], "lds_bytes_per_team": dom["lds_bytes"],
+                     "both_launches": {"ms": r32["kern_ms"], "algorithmic_flops": fs + fd + f64,
+                                       "fp64_flops": f64, "tflops": (fs + fd + f64) / (r32["kern_ms"] * 1e-3) / 1e12},
+                     "kernels": kernels},
         "cpu_baseline": cpu,
         "status_flagged": {"fp32": int(((r32["status"] & 17) != 0).sum()),
                            "fp64": int(((r64["status"] & 17) != 0).sum())},
@@ -218,8 +241,8 @@ def run_mixed(args):
     graph_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
     status = out["status"].cpu().numpy()
     modes = out["mode"].cpu().numpy()[:batch.contact_off[-1]]
-    f32, f64 = algorithmic_flops(batch, out["mode"].cpu().numpy(), p.ncp_sweeps)
-    achieved = (f32 + f64) / (graph_ms * 1e-3) / 1e12
+    fs, fd, f64 = algorithmic_flops(batch, out["mode"].cpu().numpy(), p.ncp_sweeps)
+    achieved = (fs + fd + f64) / (graph_ms * 1e-3) / 1e12
     value = batch.n_env * args.steps / wall
     line = {
         "metric": "step-derivative evals/sec (ragged trees 7-40 dof, 0-16 contacts), FP32 planned graph launch",
@@ -237,6 +260,47 @@ def run_mixed(args):
                      "jacobian> class launches", "kernel_ms": graph_ms},
         "autotune": table,
         "status_flagged": int(((status & 17) != 0).sum()),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_rollout(args):
+    """Differentiable rollouts: 1024 tree36 environments, 200 steps, FP32,
+    loss |p_base(q_T) - target|^2, gradient with respect to every torque,
+    checkpoints every 20 steps (forward, recomputation and reverse sweep all
+    in the library's fused step/position-update launches)."""
+    import torch
+    from paper_2409_07107_amd import dsim, rollout, scenes
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    n, T, C = 1024, 200, 20
+    batch = scenes.make("tree36", n, seed=0)
+    db = dsim.DeviceBatch(batch, precision=dsim.F32)
+    rng = np.random.default_rng(1)
+    taus = torch.as_tensor(rng.normal(scale=0.5, size=(T, db.n_dof)), dtype=db.dtype, device=db.device)
+    targets = np.stack([batch.q[batch.cfg_off[e]:batch.cfg_off[e] + 3] + rng.normal(scale=0.1, size=3)
+                        for e in range(n)])
+    lf = rollout.base_position_loss(db, targets)
+    reps = max(1, min(args.steps, 3))
+    rollout.rollout_gradient(db, db.q, db.v, taus, lf, checkpoint=C)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        loss, grad, info = rollout.rollout_gradient(db, db.q, db.v, taus, lf, checkpoint=C)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    status = info["status"].cpu().numpy()
+    line = {
+        "metric": "rollout gradient env-steps/sec (36-dof tree, 8 contacts, 200 steps, checkpoint 20), FP32",
+        "value": n * T / wall, "unit": "env-steps/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tree36 x 1024, 200 steps, torques N(0, 0.5^2), base-position loss; forward + "
+                               "recompute + reverse per rollout", "n_env": n, "steps": T, "checkpoint": C,
+                   "seed": 0},
+        "launches_per_rollout": T + (T - T // C) + 2 * T,
+        "flagged_envs": int(((status & 17) != 0).sum()),
+        "finite_gradients": bool(torch.isfinite(grad).all()),
     }
     print(json.dumps(line), flush=True)
 
@@ -262,8 +326,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-f32", action="store_true",
                     help="time only the FP32 launch and print no JSON line (for profiler runs)")
-    ap.add_argument("--workload", choices=("tree36", "mixed"), default="tree36",
-                    help="tree36 (the headline line) or the ragged mixed batch")
+    ap.add_argument("--workload", choices=("tree36", "mixed", "rollout"), default="tree36",
+                    help="tree36 (the headline line), the ragged mixed batch, or 200-step rollouts")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run one plain copy of BYTES and exit (counter calibration)")
     args = ap.parse_args()
@@ -276,6 +340,9 @@ def main():
         return
     if args.workload == "mixed":
         run_mixed(args)
+        return
+    if args.workload == "rollout":
+        run_rollout(args)
         return
     run(args)
 

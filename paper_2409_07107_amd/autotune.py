@@ -124,19 +124,43 @@ def lds_bytes(db, plan, p):
             for c in plan.classes]
 
 
+def _launch_class(db, plan, c, p, out, q, v, tau, gbar):
+    pc = dsim.CParams.from_buffer_copy(p)
+    pc.threads = c.threads
+    if plan.entry == dsim.ENTRY_JACOBIAN:
+        dsim.step_jacobian(db, q, v, tau, pc, out=out, cb=c.cb)
+    elif plan.entry == dsim.ENTRY_VJP:
+        dsim.step_vjp(db, gbar, q, v, tau, pc, out=out, cb=c.cb)
+    elif plan.entry == dsim.ENTRY_STEP:
+        dsim.step(db, q, v, tau, pc, out=out, cb=c.cb)
+    else:
+        raise ValueError("plans cover the step, Jacobian and VJP entries")
+
+
 def run_plan(db, plan, p, out, q=None, v=None, tau=None, gbar=None):
-    """Issue every launch of the plan on torch's current stream."""
-    for c in plan.classes:
-        pc = dsim.CParams.from_buffer_copy(p)
-        pc.threads = c.threads
-        if plan.entry == dsim.ENTRY_JACOBIAN:
-            dsim.step_jacobian(db, q, v, tau, pc, out=out, cb=c.cb)
-        elif plan.entry == dsim.ENTRY_VJP:
-            dsim.step_vjp(db, gbar, q, v, tau, pc, out=out, cb=c.cb)
-        elif plan.entry == dsim.ENTRY_STEP:
-            dsim.step(db, q, v, tau, pc, out=out, cb=c.cb)
-        else:
-            raise ValueError("plans cover the step, Jacobian and VJP entries")
+    """Issue every launch of the plan.  One class runs on torch's current
+    stream; several classes run on side streams forked from it and joined
+    back, so that their launches can overlap (and become parallel branches
+    of a captured graph).  The classes write disjoint environments; the
+    derivative entries of different classes must not share a workspace, so
+    each side stream's class gets its own."""
+    import torch
+    if len(plan.classes) == 1:
+        _launch_class(db, plan, plan.classes[0], p, out, q, v, tau, gbar)
+        return out
+    cur = torch.cuda.current_stream()
+    if not hasattr(plan, "_streams") or len(plan._streams) != len(plan.classes):
+        plan._streams = [torch.cuda.Stream() for _ in plan.classes]
+        plan._ws = [None] * len(plan.classes)
+    fork = torch.cuda.Event()
+    fork.record(cur)
+    for i, (c, s) in enumerate(zip(plan.classes, plan._streams)):
+        s.wait_event(fork)
+        with torch.cuda.stream(s):
+            with db.private_workspace(i):
+                _launch_class(db, plan, c, p, out, q, v, tau, gbar)
+    for s in plan._streams:
+        cur.wait_stream(s)
     return out
 
 

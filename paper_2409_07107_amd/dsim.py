@@ -187,6 +187,7 @@ class DeviceBatch:
         self.n_contact = int(batch.contact_off[-1])
         self.n_jac = int(jac_offsets(batch.dof_off)[-1])
         self._ws = {}
+        self._slot = 0
 
     def params(self, **overrides) -> CParams:
         p = params(self.precision, **overrides)
@@ -200,14 +201,30 @@ class DeviceBatch:
         return p
 
     def workspace(self, p: CParams, entry: int):
+        """The workspace of an entry (one per concurrent slot, see
+        private_workspace)."""
         import torch
         nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(self.c), ctypes.byref(p), int(entry)))
         if nbytes == 0:
             return None, 0
-        key = (entry, nbytes)
+        key = (self._slot, nbytes)
         if key not in self._ws:
             self._ws[key] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self._ws[key], nbytes
+
+    def private_workspace(self, slot: int):
+        """Context in which calls use workspace slot `slot`: calls that may
+        run concurrently (on different streams) must use different slots."""
+        import contextlib
+
+        @contextlib.contextmanager
+        def ctx():
+            old, self._slot = self._slot, int(slot) + 1
+            try:
+                yield
+            finally:
+                self._slot = old
+        return ctx()
 
     def lds_bytes(self, p: CParams, entry: int) -> int:
         return int(lib().dsim_lds_bytes(ctypes.byref(self.c), ctypes.byref(p), int(entry)))
