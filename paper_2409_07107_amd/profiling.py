@@ -54,9 +54,10 @@ def kernel_stats(d: str, substr: str) -> list[dict]:
     return rows
 
 
-def counter_per_dispatch(d: str, counter: str, substr: str) -> tuple[float, int]:
-    """Mean over matching dispatches of the counter summed over its
-    instances (one row per dispatch and counter in rocprofv3's CSV)."""
+def counter_per_dispatch(d: str, counter: str, substr: str, first: int = 0) -> tuple[float, int]:
+    """Mean over matching dispatches (the first `first` of them when > 0) of
+    the counter summed over its instances (one row per dispatch and counter
+    in rocprofv3's CSV)."""
     per = {}
     with open(_find(d, "counter_collection.csv")) as fh:
         for r in csv.DictReader(fh):
@@ -66,6 +67,9 @@ def counter_per_dispatch(d: str, counter: str, substr: str) -> tuple[float, int]
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
     if not per:
         raise ValueError(f"no {counter} rows for kernels matching {substr!r} in {d}")
+    if first > 0:
+        keep = sorted(per, key=int)[:first]
+        per = {k: per[k] for k in keep}
     return sum(per.values()) / len(per), len(per)
 
 
@@ -85,15 +89,15 @@ def cmd_stats(a):
 
 def cmd_traffic(a):
     kib = 1024.0
-    f_k, n_f = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
-    w_k, n_w = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
+    f_k, n_f = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel, a.first)
+    w_k, n_w = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel, a.first)
     cf_k, _ = counter_per_dispatch(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
     cw_k, _ = counter_per_dispatch(a.copy_write, "WRITE_SIZE", a.copy_kernel)
     ff = a.copy_bytes / (cf_k * kib)
     wf = a.copy_bytes / (cw_k * kib)
     fetch = f_k * kib * ff
     write = w_k * kib * wf
-    out = dict(kernel=a.kernel, source_sha1=source_digest(), command=a.cmd,
+    out = dict(kernel=a.kernel, source_sha1=source_digest(), command=a.cmd, dispatches_used=a.first or "all",
                fetch_kib_per_dispatch=f_k, write_kib_per_dispatch=w_k, dispatches=[n_f, n_w],
                copy_bytes=a.copy_bytes, copy_fetch_kib=cf_k, copy_write_kib=cw_k,
                fetch_scale=ff, write_scale=wf, fetch_bytes=fetch, write_bytes=write,
@@ -120,6 +124,7 @@ def main():
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--kernel", required=True)
     t.add_argument("--copy-kernel", required=True)
+    t.add_argument("--first", type=int, default=0, help="use only the first N matching dispatches")
     t.add_argument("--cmd", required=True)
     t.add_argument("--out", required=True)
     a = ap.parse_args()

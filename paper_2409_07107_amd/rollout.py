@@ -30,12 +30,14 @@ def rollout(db, q0, v0, taus, p=None):
     return q, v, status
 
 
-def rollout_gradient(db, q0, v0, taus, loss_fn, checkpoint=20, p=None):
+def rollout_gradient(db, q0, v0, taus, loss_fn, checkpoint=20, p=None, state_adjoint=None):
     """Loss on the final state and its gradient with respect to taus
     (T x sum n_v).  `loss_fn(q_T, v_T)` returns (loss per env, tangent adjoint
-    of q_T [sum n_v], adjoint of v_T [sum n_v]).  Returns
-    (loss, grad_taus, info) with info holding q_T, v_T, the OR of all status
-    words and the adjoints of the initial state."""
+    of q_T [sum n_v], adjoint of v_T [sum n_v]).  `state_adjoint(t, q_t, v_t)`
+    (optional) returns the adjoints (tangent on q, on v) of a loss term on an
+    intermediate state t = 1 .. T-1, or None.  Returns (loss, grad_taus,
+    info) with info holding q_T, v_T, the OR of all status words and the
+    adjoints of the initial state."""
     p = p or db.params()
     T = int(taus.shape[0])
     C = max(1, int(checkpoint))
@@ -62,6 +64,11 @@ def rollout_gradient(db, q0, v0, taus, loss_fn, checkpoint=20, p=None):
             o = dsim.step_integrate_vjp(db, a_q.contiguous(), a_v.contiguous(), qs[i], vs[i], taus[t], p)
             a_q, a_v = o["a_q"], o["a_v"]
             grads[t] = o["g_tau"]
+            if state_adjoint is not None and t > 0:
+                extra = state_adjoint(t, qs[i], vs[i])
+                if extra is not None:
+                    a_q = a_q + extra[0]
+                    a_v = a_v + extra[1]
     return loss, grads, dict(q=q, v=v, status=status, a_q0=a_q, a_v0=a_v)
 
 

@@ -378,5 +378,7 @@ def concat(batches) -> Batch:
     for b in batches:
         recs += [b.env_record(e) for e in range(b.n_env)]
     b0 = batches[0]
-    return _assemble(recs, dt=b0.dt, gravity=b0.gravity, gap_mode=b0.gap_mode,
-                     name="+".join(b.name for b in batches))
+    out = _assemble(recs, dt=b0.dt, gravity=b0.gravity, gap_mode=b0.gap_mode,
+                    name="+".join(b.name for b in batches))
+    out.kp, out.kd = b0.kp, b0.kd
+    return out
