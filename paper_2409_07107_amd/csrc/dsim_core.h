@@ -20,6 +20,7 @@
 
 #include <stddef.h>
 #include <stdint.h>
+#include <limits.h>
 
 #ifdef DSIM_HOST_BUILD
 #include <cmath>
@@ -54,6 +55,58 @@ struct Team {
     }
 #endif
 };
+
+// Slots of the team reductions: one per wavefront of the largest team (256
+// threads); the host build (a debugging build whose team threads are plain
+// threads) uses one per thread.
+#ifdef DSIM_HOST_BUILD
+constexpr int kRedSlots = 256;
+#else
+constexpr int kRedSlots = 4;
+#endif
+
+// Maximum of (v, i) over the team: the larger value wins, equal values go to
+// the smaller index, so that a strided scan in increasing index order
+// followed by this reduction picks what one serial scan with a strict
+// comparison picks.  Threads without a candidate pass (-1, INT_MAX).  Every
+// thread gets the result.  The slots are reused: a caller separates two
+// calls by at least one team barrier after the first call returns.
+DSIM_HD inline void team_argmax(const Team& T, double* redv, int* redi, double& v, int& i) {
+#ifdef DSIM_HOST_BUILD
+    redv[T.tid] = v;
+    redi[T.tid] = i;
+    T.sync();
+    v = redv[0];
+    i = redi[0];
+    for (int w = 1; w < T.nt; ++w)
+        if (redv[w] > v || (redv[w] == v && redi[w] < i)) {
+            v = redv[w];
+            i = redi[w];
+        }
+#else
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(i, off, 64);
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+    if (T.lane == 0) {
+        redv[T.wave] = v;
+        redi[T.wave] = i;
+    }
+    T.sync();
+    const int nw = (T.nt + 63) >> 6;
+    v = redv[0];
+    i = redi[0];
+    for (int w = 1; w < nw; ++w)
+        if (redv[w] > v || (redv[w] == v && redi[w] < i)) {
+            v = redv[w];
+            i = redi[w];
+        }
+#endif
+}
 
 // status bits and modes (mirror include/dsim.h)
 enum { ST_NCP = 1, ST_RANK = 2, ST_DEGEN = 4, ST_NONFINITE = 8, ST_POLISH = 16, ST_SIZE = 32 };
@@ -182,6 +235,8 @@ struct Env {
     double *vrow, *vcol, *vdiag;
     double *Gd, *gd, *Ld, *Ld1, *dfr;
     double *A, *Z, *Ysc, *rhs, *X, *ytmp, *dsig, *dsc;
+    double* redv;  // team reductions: one (value, index) slot per wavefront
+    int* redi;
 };
 
 template <class T>
@@ -304,6 +359,8 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.ytmp = take<double>(p, K, tot);
     E.dsig = take<double>(p, K, tot);
     E.dsc = take<double>(p, 4, tot);
+    E.redv = take<double>(p, kRedSlots, tot);
+    E.redi = take<int>(p, kRedSlots, tot);
     if (deriv) {
         E.Vp = take<double>(p, 6 * NB, tot);
         E.gint = take<double>(p, NV, tot);

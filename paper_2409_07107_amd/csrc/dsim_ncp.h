@@ -37,7 +37,9 @@ DSIM_HD inline void slip_direction(R l1, R l2, R e0, R e1, R beta1, R beta2, R r
         if (sn <= R(0)) sn = R(0.5) * sv;
         const R ds = fabs(sn - sv);
         sv = sn;
-        if (ds <= R(4) * R(sizeof(R) == 4 ? 1.2e-7 : 2.3e-16) * (sv + p1)) break;
+        // FP32 stops at 1e-6 relative: closer to its rounding unit the step
+        // only oscillates until the iteration cap
+        if (ds <= R(sizeof(R) == 4 ? 1e-6 : 9.2e-16) * (sv + p1)) break;
     }
     const R d1 = sv + p1, d2 = sv + p2;
     const R q1 = d1 > tiny ? beta1 / d1 : R(0), q2 = d2 > tiny ? beta2 / d2 : R(0);
@@ -103,7 +105,12 @@ DSIM_HD inline bool slide_newton(const R* W, const R* b, R mu, R* lam) {
         const R c00 = Jm[4] * Jm[8] - Jm[5] * Jm[7], c01 = Jm[5] * Jm[6] - Jm[3] * Jm[8],
                 c02 = Jm[3] * Jm[7] - Jm[4] * Jm[6];
         const R det = Jm[0] * c00 + Jm[1] * c01 + Jm[2] * c02;
-        if (!(fabs(det) > R(0))) return false;
+        // a (numerically) singular Jacobian: the impulse is not determined
+        // along some direction, and a Newton step along it is unbounded
+        R rn[3];
+        for (int i = 0; i < 3; ++i)
+            rn[i] = fabs(Jm[3 * i]) + fabs(Jm[3 * i + 1]) + fabs(Jm[3 * i + 2]);
+        if (!(fabs(det) > R(sizeof(R) == 4 ? 1e-6 : 1e-12) * rn[0] * rn[1] * rn[2])) return false;
         const R id = R(1) / det;
         // step = -J^-1 f (adjugate)
         const R d0 = -(c00 * f0 + (Jm[2] * Jm[7] - Jm[1] * Jm[8]) * f1 + (Jm[1] * Jm[5] - Jm[2] * Jm[4]) * f2) * id;
@@ -118,7 +125,9 @@ DSIM_HD inline bool slide_newton(const R* W, const R* b, R mu, R* lam) {
 
 template <class R>
 DSIM_HD inline int local_solve(const R* W, const R* Wi, const R* b, R mu, R* lam, int prev_mode) {
-    if (b[2] >= R(0)) {
+    // separating, or a point whose normal velocity no impulse changes (its
+    // normal row of the block is zero up to rounding)
+    if (b[2] >= R(0) || !(W[8] > R(sizeof(R) == 4 ? 1e-6 : 1e-12) * (W[0] + W[4] + W[8]))) {
         lam[0] = lam[1] = lam[2] = 0;
         return BRK;
     }
@@ -176,10 +185,23 @@ DSIM_HD inline int local_solve(const R* W, const R* Wi, const R* b, R mu, R* lam
         rhi *= R(2);
         ghi = gfun(rhi);
     }
+    if (!(ghi > R(0))) {
+        // no sliding impulse makes the normal velocity vanish (a singular
+        // block): the sticking candidate pulled radially onto the cone
+        const R sn = s[2] > R(0) ? s[2] : R(0);
+        const R f = (nt > mu * sn && nt > R(0)) ? mu * sn / nt : R(1);
+        lam[0] = s[0] * f;
+        lam[1] = s[1] * f;
+        lam[2] = sn;
+        return sn > R(0) ? SLD : BRK;
+    }
     R r = rhi;
-    if (ghi > R(0)) {
+    {
         int side = 0;
-        const R rtol = R(sizeof(R) == 4 ? 1e-7 : 1e-15);
+        // bracket width at which the search stops; in FP32 a width near the
+        // rounding unit is rarely reached and the search would run to its cap
+        // (the refinement that follows works in FP64 anyway)
+        const R rtol = R(sizeof(R) == 4 ? 1e-6 : 1e-15);
         for (int it = 0; it < 100; ++it) {
             r = (rlo * ghi - rhi * glo) / (ghi - glo);
             if (!(r > rlo && r < rhi)) r = R(0.5) * (rlo + rhi);
@@ -381,48 +403,68 @@ DSIM_HD void factor_A(const Team& T, Env<R>& E, double rank_tol) {
     const int m = E.hdr[1];
     const int nst = 3 * E.hdr[2];
     double* A = E.A;
-    if (T.tid == 0) {
-        for (int i = 0; i < m; ++i) {
-            E.rperm[i] = i;
-            E.cperm[i] = i;
+    for (int i = T.tid; i < m; i += T.nt) {
+        E.rperm[i] = i;
+        E.cperm[i] = i;
+    }
+    // largest entry (a team reduction; the index is unused)
+    double scale = -1;
+    int si = INT_MAX;
+    for (int idx = T.tid; idx < m * m; idx += T.nt) {
+        const double a = fabs(A[idx]);
+        if (a > scale) {
+            scale = a;
+            si = idx;
         }
-        E.hdr[4] = m;
     }
+    team_argmax(T, E.redv, E.redi, scale, si);
     T.sync();
-    double scale = 0;
-    for (int i = 0; i < m * m; ++i) {
-        const double a = fabs(A[i]);
-        scale = a > scale ? a : scale;
-    }
     const double tol = rank_tol * (scale > 0 ? scale : 1.0);
     int rank = 0;
     bool stick_phase = nst > 0;
     for (int p = 0; p < m; ++p) {
-        // pivot choice (every thread computes the same, reading A)
+        // pivot choice: a strided scan per thread, then the team maximum
+        // (first maximum in index order, as one serial scan would find)
         int pr = -1, pc = -1;
         double best = -1;
+        int bi = INT_MAX;
         if (stick_phase && p < nst) {
-            for (int i = p; i < nst; ++i) {
+            for (int i = p + T.tid; i < nst; i += T.nt) {
                 const double a = fabs(A[i * m + i]);
                 if (a > best) {
                     best = a;
-                    pr = i;
-                    pc = i;
+                    bi = i;
                 }
             }
-            if (best <= tol) stick_phase = false;
+            team_argmax(T, E.redv, E.redi, best, bi);
+            if (bi != INT_MAX) {
+                pr = bi;
+                pc = bi;
+            }
+            if (best <= tol) {
+                stick_phase = false;
+                T.sync();  // the reduction slots are reused below
+            }
         }
         if (!(stick_phase && p < nst)) {
             best = -1;
-            for (int i = p; i < m; ++i)
-                for (int j = p; j < m; ++j) {
-                    const double a = fabs(A[i * m + j]);
-                    if (a > best) {
-                        best = a;
-                        pr = i;
-                        pc = j;
-                    }
+            bi = INT_MAX;
+            const int rem = m - p;
+            for (int idx = T.tid; idx < rem * rem; idx += T.nt) {
+                const int i = p + idx / rem, j = p + idx % rem;
+                const double a = fabs(A[i * m + j]);
+                if (a > best) {
+                    best = a;
+                    bi = i * m + j;
                 }
+            }
+            team_argmax(T, E.redv, E.redi, best, bi);
+            pr = -1;
+            pc = -1;
+            if (bi != INT_MAX) {
+                pr = bi / m;
+                pc = bi - pr * m;
+            }
         }
         if (best <= tol || pr < 0) break;
         T.sync();

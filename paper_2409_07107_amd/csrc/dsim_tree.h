@@ -435,24 +435,57 @@ DSIM_HD void delassus(const Team& T, Env<R>& E, const Params& P) {
     }
     T.sync();
     for (int c = T.tid; c < E.nc; c += T.nt) {
-        double W[9];
+        // pseudo-inverse of the contact's 3x3 block (symmetric positive
+        // semidefinite) by Jacobi rotations in FP64; eigenvalues below a
+        // relative threshold count as zero.  A contact point that cannot move
+        // in some direction has a singular block, and the Gauss-Seidel
+        // sticking impulse is then the minimum-norm one: an inverse of the
+        // rounded block would turn rounding noise along that direction into
+        // an unbounded impulse.
+        double a[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) W[3 * i + j] = E.Gd[(3 * c + i) * k + 3 * c + j];
-        const double eps = (W[0] + W[4] + W[8]) * 1e-12;
-        W[0] += eps; W[4] += eps; W[8] += eps;
-        const double c00 = W[4] * W[8] - W[5] * W[7], c01 = W[5] * W[6] - W[3] * W[8],
-                     c02 = W[3] * W[7] - W[4] * W[6];
-        const double id = 1.0 / (W[0] * c00 + W[1] * c01 + W[2] * c02);
+            for (int j = 0; j < 3; ++j)
+                a[3 * i + j] = 0.5 * (E.Gd[(3 * c + i) * k + 3 * c + j] + E.Gd[(3 * c + j) * k + 3 * c + i]);
+        for (int sweep = 0; sweep < 8; ++sweep) {
+            const double off = a[1] * a[1] + a[2] * a[2] + a[5] * a[5];
+            const double dia = a[0] * a[0] + a[4] * a[4] + a[8] * a[8];
+            if (!(off > 1e-32 * dia)) break;
+            for (int pq = 0; pq < 3; ++pq) {
+                const int pp = pq == 2 ? 1 : 0, qq = pq == 0 ? 1 : 2;
+                const double apq = a[3 * pp + qq];
+                if (apq == 0.0) continue;
+                // rotation annihilating a_pq (symmetric Schur decomposition)
+                const double th = (a[3 * qq + qq] - a[3 * pp + pp]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int r = 0; r < 3; ++r) {  // a <- a G (columns p, q)
+                    const double x = a[3 * r + pp], y = a[3 * r + qq];
+                    a[3 * r + pp] = cs * x - sn * y;
+                    a[3 * r + qq] = sn * x + cs * y;
+                }
+                for (int r = 0; r < 3; ++r) {  // a <- G^T a (rows p, q)
+                    const double x = a[3 * pp + r], y = a[3 * qq + r];
+                    a[3 * pp + r] = cs * x - sn * y;
+                    a[3 * qq + r] = sn * x + cs * y;
+                }
+                for (int r = 0; r < 3; ++r) {  // V <- V G
+                    const double x = V[3 * r + pp], y = V[3 * r + qq];
+                    V[3 * r + pp] = cs * x - sn * y;
+                    V[3 * r + qq] = sn * x + cs * y;
+                }
+            }
+        }
+        const double lmax = fmax(a[0], fmax(a[4], a[8]));
+        const double cut = lmax * (sizeof(R) == 4 ? 1e-6 : 1e-12);
+        double wi[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int e = 0; e < 3; ++e) {
+            const double l = a[4 * e];
+            if (!(l > cut)) continue;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) wi[3 * i + j] += V[3 * i + e] * V[3 * j + e] / l;
+        }
         R* Wi = E.Winv + 9 * c;
-        Wi[0] = R(c00 * id);
-        Wi[1] = R((W[2] * W[7] - W[1] * W[8]) * id);
-        Wi[2] = R((W[1] * W[5] - W[2] * W[4]) * id);
-        Wi[3] = R(c01 * id);
-        Wi[4] = R((W[0] * W[8] - W[2] * W[6]) * id);
-        Wi[5] = R((W[2] * W[3] - W[0] * W[5]) * id);
-        Wi[6] = R(c02 * id);
-        Wi[7] = R((W[1] * W[6] - W[0] * W[7]) * id);
-        Wi[8] = R((W[0] * W[4] - W[1] * W[3]) * id);
+        for (int i = 0; i < 9; ++i) Wi[i] = R(wi[i]);
     }
     T.sync();
 }
