@@ -60,9 +60,9 @@ struct Team {
 // threads); the host build (a debugging build whose team threads are plain
 // threads) uses one per thread.
 #ifdef DSIM_HOST_BUILD
-constexpr int kRedSlots = 256;
+constexpr int kRedSlots = 512;
 #else
-constexpr int kRedSlots = 4;
+constexpr int kRedSlots = 8;
 #endif
 
 // Maximum of (v, i) over the team: the larger value wins, equal values go to
@@ -105,6 +105,41 @@ DSIM_HD inline void team_argmax(const Team& T, double* redv, int* redi, double& 
             v = redv[w];
             i = redi[w];
         }
+#endif
+}
+
+// Maxima of two values over the team (NaN never wins), returned to every
+// thread; the same slot reuse rule as team_argmax.
+DSIM_HD inline void team_max2(const Team& T, double* redv, double& a, double& b) {
+#ifdef DSIM_HOST_BUILD
+    redv[2 * T.tid] = a;
+    redv[2 * T.tid + 1] = b;
+    T.sync();
+    a = redv[0];
+    b = redv[1];
+    for (int w = 1; w < T.nt; ++w) {
+        a = redv[2 * w] > a ? redv[2 * w] : a;
+        b = redv[2 * w + 1] > b ? redv[2 * w + 1] : b;
+    }
+#else
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double oa = __shfl_xor(a, off, 64);
+        const double ob = __shfl_xor(b, off, 64);
+        a = oa > a ? oa : a;
+        b = ob > b ? ob : b;
+    }
+    if (T.lane == 0) {
+        redv[2 * T.wave] = a;
+        redv[2 * T.wave + 1] = b;
+    }
+    T.sync();
+    const int nw = (T.nt + 63) >> 6;
+    a = redv[0];
+    b = redv[1];
+    for (int w = 1; w < nw; ++w) {
+        a = redv[2 * w] > a ? redv[2 * w] : a;
+        b = redv[2 * w + 1] > b ? redv[2 * w + 1] : b;
+    }
 #endif
 }
 
@@ -358,7 +393,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.X = take<double>(p, K, tot);
     E.ytmp = take<double>(p, K, tot);
     E.dsig = take<double>(p, K, tot);
-    E.dsc = take<double>(p, 4, tot);
+    E.dsc = take<double>(p, 8, tot);
     E.redv = take<double>(p, kRedSlots, tot);
     E.redi = take<int>(p, kRedSlots, tot);
     if (deriv) {

@@ -533,46 +533,67 @@ DSIM_HD inline void lu_solve(const double* A, int m, int rank, const int* rperm,
 // scale, impulse rows by the impulse scale).  Uses Ld and dsig.
 template <class R>
 DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
-    const int k = E.k;
-    if (T.tid == 0) {
-        int m = 0, nstk = 0;
-        for (int pass = 0; pass < 2; ++pass)
-            for (int c = 0; c < E.nc; ++c) {
-                const int md = E.cmode[c];
-                if ((pass == 0 && md == STK) || (pass == 1 && md == SLD)) {
-                    for (int a = 0; a < 3; ++a) {
-                        E.vctc[m] = c;
-                        E.vcmp[m] = a;
-                        ++m;
-                    }
-                    if (md == STK) ++nstk;
-                }
-                if (pass == 1 && md == SLD) {
-                    const double s0 = E.dsig[3 * c], s1 = E.dsig[3 * c + 1];
-                    double ns = sqrt(s0 * s0 + s1 * s1);
-                    double u0, u1;
-                    if (ns > 1e-300) {
-                        u0 = s0 / ns;
-                        u1 = s1 / ns;
-                    } else {
-                        // no slip yet: hold the friction direction
-                        const double l0 = E.Ld[3 * c], l1 = E.Ld[3 * c + 1];
-                        const double nl = sqrt(l0 * l0 + l1 * l1);
-                        u0 = nl > 0 ? -l0 / nl : 1.0;
-                        u1 = nl > 0 ? -l1 / nl : 0.0;
-                        ns = 1e-300;
-                    }
-                    double* f = E.dfr + 4 * c;
-                    f[0] = u0;
-                    f[1] = u1;
-                    f[2] = double(E.mu[c]) * E.Ld[3 * c + 2] / ns;  // mu Lam_N / |sigma_T|
-                }
+    const int k = E.k, nc = E.nc;
+    // unknowns: every thread counts the active contacts (sticking first,
+    // then sliding) and thread c fills the slots of contact c
+    int nstk = 0, nact = 0;
+    for (int c = 0; c < nc; ++c) {
+        const int md = E.cmode[c];
+        nstk += md == STK;
+        nact += md != BRK;
+    }
+    const int m = 3 * nact;
+    for (int c = T.tid; c < nc; c += T.nt) {
+        const int md = E.cmode[c];
+        if (md == BRK) continue;
+        int before = 0;  // active contacts ahead of c in the unknowns
+        for (int d = 0; d < c; ++d) before += E.cmode[d] == md;
+        const int slot = 3 * (md == STK ? before : nstk + before);
+        for (int a = 0; a < 3; ++a) {
+            E.vctc[slot + a] = c;
+            E.vcmp[slot + a] = a;
+        }
+        if (md == SLD) {
+            const double s0 = E.dsig[3 * c], s1 = E.dsig[3 * c + 1];
+            double ns = sqrt(s0 * s0 + s1 * s1);
+            double u0, u1;
+            if (ns > 1e-300) {
+                u0 = s0 / ns;
+                u1 = s1 / ns;
+            } else {
+                // no slip yet: hold the friction direction
+                const double l0 = E.Ld[3 * c], l1 = E.Ld[3 * c + 1];
+                const double nl = sqrt(l0 * l0 + l1 * l1);
+                u0 = nl > 0 ? -l0 / nl : 1.0;
+                u1 = nl > 0 ? -l1 / nl : 0.0;
+                ns = 1e-300;
             }
+            double* f = E.dfr + 4 * c;
+            f[0] = u0;
+            f[1] = u1;
+            f[2] = double(E.mu[c]) * E.Ld[3 * c + 2] / ns;  // mu Lam_N / |sigma_T|
+        }
+    }
+    if (T.tid == 0) {
         E.hdr[1] = m;
         E.hdr[2] = nstk;
     }
-    T.sync();
-    const int m = E.hdr[1];
+    // residual scales (largest free velocity, with the gravity step, and
+    // largest impulse) as a team reduction
+    double smax = 1e-300, lmax = 1e-300;
+    for (int r = T.tid; r < k; r += T.nt) {
+        const double a = fabs(E.gd[r]);
+        smax = a > smax ? a : smax;
+        const double l = fabs(E.Ld[r]);
+        lmax = l > lmax ? l : lmax;
+    }
+    team_max2(T, E.redv, smax, lmax);  // its barrier also publishes the slots
+    const double sg = P.dt * (fabs(P.gx) + fabs(P.gy) + fabs(P.gz));
+    smax = smax > sg ? smax : sg;
+    if (T.tid == 0) {
+        E.dsc[4] = smax;
+        E.dsc[5] = lmax;
+    }
     for (int idx = T.tid; idx < m * m; idx += T.nt) {
         const int i = idx / m, j = idx - i * m;
         const int ci = E.vctc[i], ai = E.vcmp[i];
@@ -592,22 +613,27 @@ DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
         }
         E.A[idx] = v;
     }
+    // residual entries in parallel; their maximum and sum of squares by one
+    // thread in index order
+    for (int i = T.tid; i < m; i += T.nt) {
+        const int c = E.vctc[i], a = E.vcmp[i];
+        double f, rel;
+        if (E.cmode[c] == SLD && a < 2) {
+            const double* fr = E.dfr + 4 * c;
+            f = E.Ld[3 * c + a] + double(E.mu[c]) * E.Ld[3 * c + 2] * fr[a];
+            rel = fabs(f) / lmax;
+        } else {
+            f = E.dsig[3 * c + a];
+            rel = fabs(f) / smax;
+        }
+        E.rhs[i] = -f;
+        E.ytmp[i] = rel;
+    }
+    T.sync();
     if (T.tid == 0) {
-        double smax, lmax;
-        scales(E, P, smax, lmax);
         double res = 0, nrm = 0;
         for (int i = 0; i < m; ++i) {
-            const int c = E.vctc[i], a = E.vcmp[i];
-            double f, rel;
-            if (E.cmode[c] == SLD && a < 2) {
-                const double* fr = E.dfr + 4 * c;
-                f = E.Ld[3 * c + a] + double(E.mu[c]) * E.Ld[3 * c + 2] * fr[a];
-                rel = fabs(f) / lmax;
-            } else {
-                f = E.dsig[3 * c + a];
-                rel = fabs(f) / smax;
-            }
-            E.rhs[i] = -f;
+            const double rel = E.ytmp[i];
             res = rel > res ? rel : res;
             nrm += rel * rel;
         }
@@ -623,7 +649,9 @@ DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
 // change mode (penetrating breaking contact -> sticking, negative normal
 // impulse -> breaking, sticking impulse outside the cone -> sliding, slip not
 // opposed by friction -> sticking) and the iteration continues; a step that
-// increases the residual of the same mode set is halved.  Returns true on a
+// increases the residual of the same mode set is halved once, then taken
+// (longer backtracking spent evaluations without helping: more environments
+// stalled than with the nearly plain Newton step).  Returns true on a
 // consistent solution.
 template <class R>
 DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
@@ -636,8 +664,10 @@ DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
         E.dsc[0] = 1e300;
     }
     T.sync();
-    // bounded work: at most 8 (newton_iters + 1) evaluations per refinement
-    for (int guard = 0; guard < 8 * (P.newton_iters + 1); ++guard) {
+    // bounded work: at most 4 (newton_iters + 1) evaluations per refinement;
+    // a refinement that has not converged by then is rarely rescued by more
+    // evaluations, and the next round restarts from more sweeps
+    for (int guard = 0; guard < 4 * (P.newton_iters + 1); ++guard) {
         fp64_sigma(T, E);
         newton_system(T, E, P);
         const int m = E.hdr[1];
@@ -645,7 +675,7 @@ DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
             const double res = E.dsc[1], nrm = E.dsc[3];
             const int conv = (res <= P.ncp_tol) ? 1 : 0;
             int back = 0;
-            if (!conv && since > 0 && nrm > E.dsc[0] && E.hdr[12] < 12) {
+            if (!conv && since > 0 && nrm > E.dsc[0] && E.hdr[12] < 1) {
                 back = 1;
                 E.hdr[12] += 1;
                 for (int r = 0; r < k; ++r) E.Ld[r] = 0.5 * (E.Ld1[r] + E.Ld[r]);
@@ -663,8 +693,7 @@ DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
             // mode inequalities are checked at a solution of the mode
             // equations, or when Newton stalls on the current mode set
             if (conv || (!back && since >= P.newton_iters)) {
-                double smax, lmax;
-                scales(E, P, smax, lmax);
+                const double smax = E.dsc[4], lmax = E.dsc[5];  // scales of this evaluation
                 const double tl = 1e2 * P.ncp_tol;
                 for (int c = 0; c < nc; ++c) {
                     const double L0 = E.Ld[3 * c], L1 = E.Ld[3 * c + 1], L2 = E.Ld[3 * c + 2];
