@@ -184,6 +184,116 @@ def appendix_b(env: dict, res: dict | None = None):
     return dict(jac=jac, dLam=dLam, A=A, B=B, C=C, D0=D0, E=E, rhs=rhs)
 
 
+def _param_system(model: Model, q, v, tau, modes, gap_mode):
+    """The same mode system as a function of y = (v+, Lam) and the physical
+    parameters p = (body masses, friction coefficients), with (q, v, tau)
+    fixed.  A body's mass changes with its centre of mass and its rotational
+    inertia about the centre of mass held fixed."""
+    dt = model.dt
+    nv, nc, nb = model.nv, model.nc, model.nb
+    base_mass = model.mass
+
+    def F(y, p):
+        vn, Lam = y[:nv], y[nv:]
+        mass, mu = p[:nb], p[nb:]
+        a = (vn - t64(v)) / dt
+        fext = (Lam / dt).reshape(nc, 3) if nc else None
+        model.mass = mass
+        try:
+            Fdyn = dt * (model.rnea(t64(q), t64(v), a, fext_world=fext) - t64(tau))
+        finally:
+            model.mass = base_mass
+        if nc == 0:
+            return Fdyn
+        sig = model.contact_velocity(t64(q), vn)
+        if gap_mode == 1:
+            add = torch.zeros(3 * nc, dtype=F64)
+            add[2::3] = gap_terms(model, t64(q), t64(v))
+            sig = sig + add
+        rows = []
+        for i, md in enumerate(modes):
+            L = Lam[3 * i:3 * i + 3]
+            S = sig[3 * i:3 * i + 3]
+            if md == ncp.BRK:
+                rows.append(L)
+            elif md == ncp.STK:
+                rows.append(S)
+            else:
+                nt = torch.sqrt(S[0] * S[0] + S[1] * S[1])
+                rows.append(torch.stack([L[0] + mu[i] * L[2] * S[0] / nt,
+                                         L[1] + mu[i] * L[2] * S[1] / nt,
+                                         S[2]]))
+        return torch.cat([Fdyn] + rows)
+
+    return F
+
+
+def param_ift(env: dict, res: dict | None = None):
+    """dv+/d(mass, mu) by the implicit-function theorem on the raw mode
+    system (the physical-parameter columns of the same dF/dy).  Returns
+    dict(jac = (n, nb + nc), unique_v, ...): columns are the body masses,
+    then the contacts' friction coefficients."""
+    res = res or forward(env)
+    model = res["model"]
+    nv = model.nv
+    y0 = torch.cat([t64(res["vnext"]), t64(res["Lam"])])
+    p0 = torch.cat([model.mass.clone(), t64(model.mu)])
+    F = _param_system(model, env["q"], env["v"], env["tau"], res["modes"], model.gap_mode)
+    Fy, Fp = torch.autograd.functional.jacobian(F, (y0, p0))
+    Fy, Fp = Fy.numpy(), Fp.numpy()
+    U, s, Vt = np.linalg.svd(Fy)
+    smax = s.max() if s.size else 1.0
+    keep = s > 1e-12 * smax
+    X = -(Vt[keep].T @ ((U[:, keep].T @ Fp) / s[keep, None]))
+    null = Vt[~keep]
+    v_null = float(np.abs(null[:, :nv]).max()) if null.size else 0.0
+    return dict(jac=X[:nv], dLam=X[nv:], unique_v=v_null < 1e-8, v_null=v_null, Fy=Fy, Fp=Fp)
+
+
+def param_finite_differences(env: dict, res: dict | None = None, h=1e-6):
+    """Central differences of v+ in the body masses and the friction
+    coefficients (relative steps h * value); returns (jac, valid) with valid
+    False where a perturbed step changes a contact mode."""
+    res = res or forward(env)
+    model = res["model"]
+    nb, nc, nv = model.nb, model.nc, model.nv
+    mass = np.asarray(env["mass"], dtype=np.float64)
+    mu = np.asarray(env["mu"], dtype=np.float64)
+    jac = np.full((nv, nb + nc), np.nan)
+    valid = np.zeros(nb + nc, dtype=bool)
+    base_modes = list(res["modes"])
+    for col in range(nb + nc):
+        outs, same = [], True
+        if col < nb:
+            step = h * mass[col]
+        else:
+            step = h * max(mu[col - nb], 1e-3)
+        for sgn in (1.0, -1.0):
+            e = dict(env)
+            e["mass"] = mass.copy()
+            e["mu"] = mu.copy()
+            if col < nb:
+                e["mass"][col] += sgn * step
+            else:
+                e["mu"][col - nb] += sgn * step
+            r = forward(e, Lam0=res["Lam"])
+            same &= list(r["modes"]) == base_modes
+            outs.append(r["vnext"])
+        jac[:, col] = (outs[0] - outs[1]) / (2 * step)
+        valid[col] = same
+    return jac, valid
+
+
+def param_vjp(env: dict, gbar_v, res: dict | None = None):
+    """Reverse mode in the physical parameters: gbar^T dv+/d(mass, mu) split
+    into (masses, friction coefficients)."""
+    res = res or forward(env)
+    d = param_ift(env, res)
+    nb = res["model"].nb
+    g = np.asarray(gbar_v, dtype=np.float64) @ d["jac"]
+    return g[:nb], g[nb:]
+
+
 def finite_differences(env: dict, res: dict | None = None, h=1e-6, cols=None):
     """Central differences of v+ in (dq, v, tau); returns (jac, valid)."""
     res = res or forward(env)
