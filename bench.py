@@ -305,6 +305,51 @@ def run_rollout(args):
     print(json.dumps(line), flush=True)
 
 
+def run_params(args):
+    """Reverse mode in the state and the physical parameters: tree36 x 16384,
+    FP32, one dsim_step_vjp_params call per step (gbar^T dv+ with respect to
+    q, v, tau, the 31 body masses and the 8 friction coefficients), timed
+    with HIP events beside dsim_step_vjp on the same batch."""
+    import torch
+    from paper_2409_07107_amd import dsim, scenes
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    batch = scenes.make("tree36", 16384, seed=0)
+    db = dsim.DeviceBatch(batch, precision=dsim.F32)
+    p = db.params()
+    gbar = torch.as_tensor(np.random.default_rng(3).normal(size=db.n_dof), dtype=db.dtype, device=db.device)
+    out_p = dsim.step_vjp_params(db, gbar, p=p)
+    out_v = dsim.step_vjp(db, gbar, p=p)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(args.steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / args.steps
+
+    ms_p = timed(lambda: dsim.step_vjp_params(db, gbar, p=p, out=out_p))
+    ms_v = timed(lambda: dsim.step_vjp(db, gbar, p=p, out=out_v))
+    status = out_p["status"].cpu().numpy()
+    line = {
+        "metric": "step VJP evals/sec with mass and friction gradients (36-dof tree, 8 contacts), FP32",
+        "value": batch.n_env / (ms_p * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_p, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tree36 x 16384 (as the headline line); gbar ~ N(0, 1); dsim_step_vjp_params",
+                   "n_env": batch.n_env, "seed": 0},
+        "state_vjp_only": {"ms_per_step": ms_v, "value": batch.n_env / (ms_v * 1e-3)},
+        "flagged_envs": int(((status & 17) != 0).sum()),
+        "finite_gradients": bool(torch.isfinite(out_p["g_mass"]).all() and torch.isfinite(out_p["g_mu"]).all()),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_probe(nbytes):
     """One plain elementwise copy kernel (dst = src * 1 in FP32) over nbytes:
     the reference reading of the HBM byte counters (FETCH_SIZE, WRITE_SIZE)
@@ -326,8 +371,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-f32", action="store_true",
                     help="time only the FP32 launch and print no JSON line (for profiler runs)")
-    ap.add_argument("--workload", choices=("tree36", "mixed", "rollout"), default="tree36",
-                    help="tree36 (the headline line), the ragged mixed batch, or 200-step rollouts")
+    ap.add_argument("--workload", choices=("tree36", "mixed", "rollout", "params"), default="tree36",
+                    help="tree36 (the headline line), the ragged mixed batch, 200-step rollouts, or the reverse "
+                         "mode with physical-parameter gradients")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run one plain copy of BYTES and exit (counter calibration)")
     args = ap.parse_args()
@@ -343,6 +389,9 @@ def main():
         return
     if args.workload == "rollout":
         run_rollout(args)
+        return
+    if args.workload == "params":
+        run_params(args)
         return
     run(args)
 

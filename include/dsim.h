@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define DSIM_ABI_VERSION 3
+#define DSIM_ABI_VERSION 4
 
 /* return codes */
 #define DSIM_SUCCESS 0
@@ -88,7 +88,8 @@ typedef enum {
     DSIM_ENTRY_JACOBIAN = 1,
     DSIM_ENTRY_VJP = 2,
     DSIM_ENTRY_STEP_INTEGRATE = 3,
-    DSIM_ENTRY_STEP_INTEGRATE_VJP = 4
+    DSIM_ENTRY_STEP_INTEGRATE_VJP = 4,
+    DSIM_ENTRY_VJP_PARAMS = 5
 } dsim_entry;
 
 /*
@@ -225,6 +226,27 @@ int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
                       void* v_next, void* lam, int8_t* mode, int32_t* status,
                       void* g_q, void* g_v, void* g_tau,
                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Reverse mode in the physical parameters as well (derivatives with respect
+ * to physical parameters, Section II.D, by the implicit differentiation of
+ * the same mode system): everything dsim_step_vjp computes, plus
+ *   g_mass [sum n_b]: gbar^T dv+/dm_b per body (global body index), the
+ *     body's mass changing with its centre of mass and its rotational
+ *     inertia about the centre of mass held fixed;
+ *   g_mu [sum n_c]: gbar^T dv+/dmu_c per contact (zero for breaking and
+ *     sticking contacts, whose equations do not involve mu).
+ * Both are generalised forces paired with dt M^-1 P^T gbar, the vector the
+ * reverse mode already forms, so the cost over dsim_step_vjp is one pass
+ * over the bodies and contacts.  g_mu may be NULL only when the batch has
+ * no contacts.  Workspace: as dsim_step_vjp.  Errors: as dsim_step_vjp.
+ */
+int32_t dsim_step_vjp_params(const dsim_batch* batch, const dsim_params* params,
+                             const void* q, const void* v, const void* tau,
+                             const void* g_vnext,
+                             void* v_next, void* lam, int8_t* mode, int32_t* status,
+                             void* g_q, void* g_v, void* g_tau, void* g_mass, void* g_mu,
+                             void* ws, size_t ws_bytes, void* stream);
 
 /*
  * The step followed by the position update q_next = q (+) dt v_next

@@ -87,7 +87,8 @@ int team_threads(const dsim_params* p) {
 template <class R, int ENTRY>
 __global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims D, const R* q, const R* v,
                                                   const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
-                                                  int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, double* ld) {
+                                                  int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, R* o4, R* o5,
+                                                  double* ld) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     Team T;
     T.tid = threadIdx.x;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims
     }
     Env<R> E;
     carve<R>(smem, D, ENTRY, E);
-    run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, ld);
+    run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld);
 }
 
 // Tangent gradient on q -> gradient on the stored coordinates of q: per body,
@@ -169,7 +170,7 @@ int check_common(const dsim_batch* b, const dsim_params* p) {
 template <class R, int ENTRY>
 int launch_one(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
                const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status,
-               void* o1, void* o2, void* o3, double* ld, void* stream) {
+               void* o1, void* o2, void* o3, void* o4, void* o5, double* ld, void* stream) {
     const size_t bytes = team_bytes(b, p, ENTRY);
     if (bytes > kLdsLimit) return DSIM_ERR_SIZE;  // the team's working set must fit in LDS
     const int threads = team_threads(p);
@@ -186,7 +187,7 @@ int launch_one(const dsim_batch* b, const dsim_params* p, const void* q, const v
                        params_of(p), dims_of(b), static_cast<const R*>(q), static_cast<const R*>(v),
                        static_cast<const R*>(tau), static_cast<const R*>(gbar), static_cast<const R*>(gbar2),
                        static_cast<R*>(v_next), static_cast<R*>(lam), mode, status, static_cast<R*>(o1),
-                       static_cast<R*>(o2), static_cast<R*>(o3), ld);
+                       static_cast<R*>(o2), static_cast<R*>(o3), static_cast<R*>(o4), static_cast<R*>(o5), ld);
     return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
 }
 
@@ -201,33 +202,34 @@ size_t handover_bytes(const dsim_batch* b) { return size_t(b->n_env) * kLdStride
 template <class R, int ENTRY>
 int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
            const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
-           void* o2, void* o3, void* ws, size_t ws_bytes, void* stream) {
+           void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream) {
     if (b->n_env == 0) return DSIM_SUCCESS;
     if (!entry_has_derivative(ENTRY))
-        return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, nullptr,
-                                    stream);
+        return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
+                                    nullptr, stream);
     if (!ws || ws_bytes < handover_bytes(b)) return DSIM_ERR_WORKSPACE;
     if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
     double* ld = static_cast<double*>(ws);
     int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
-                                       nullptr, nullptr, ld, stream);
+                                       nullptr, nullptr, nullptr, nullptr, ld, stream);
     if (rc) return rc;
-    return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, ld, stream);
+    return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld,
+                                stream);
 }
 
 template <int ENTRY>
 int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
              const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
-             void* o2, void* o3, void* ws, size_t ws_bytes, void* stream) {
+             void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(b, p);
     if (rc) return rc;
     if (b->n_env == 0) return DSIM_SUCCESS;
     if (!q || !v || !tau || !v_next || !status || !mode || !lam) return DSIM_ERR_ARG;
     if (p->precision == DSIM_F32)
-        return launch<float, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, ws,
-                                    ws_bytes, stream);
-    return launch<double, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, ws,
-                                 ws_bytes, stream);
+        return launch<float, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
+                                    ws, ws_bytes, stream);
+    return launch<double, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
+                                 ws, ws_bytes, stream);
 }
 
 }  // namespace
@@ -378,7 +380,7 @@ size_t dsim_workspace_bytes(const dsim_batch* b, const dsim_params* p, int32_t e
 int32_t dsim_step(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
                   void* v_next, void* lam, int8_t* mode, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
     return dispatch<ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr, nullptr,
-                                nullptr, ws, ws_bytes, stream);
+                                nullptr, nullptr, nullptr, ws, ws_bytes, stream);
 }
 
 int32_t dsim_step_jacobian(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
@@ -386,7 +388,7 @@ int32_t dsim_step_jacobian(const dsim_batch* b, const dsim_params* p, const void
                            void* dvdtau, void* ws, size_t ws_bytes, void* stream) {
     if (!dvdq || !dvdv || !dvdtau || (b && b->n_env > 0 && !b->jac_off)) return DSIM_ERR_ARG;
     return dispatch<ENTRY_JAC>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, dvdq, dvdv, dvdtau,
-                               ws, ws_bytes, stream);
+                               nullptr, nullptr, ws, ws_bytes, stream);
 }
 
 int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
@@ -394,7 +396,16 @@ int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, 
                       void* g_v, void* g_tau, void* ws, size_t ws_bytes, void* stream) {
     if (!g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
     return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, nullptr, v_next, lam, mode, status, g_q, g_v, g_tau,
-                               ws, ws_bytes, stream);
+                               nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int32_t dsim_step_vjp_params(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                             const void* tau, const void* g_vnext, void* v_next, void* lam, int8_t* mode,
+                             int32_t* status, void* g_q, void* g_v, void* g_tau, void* g_mass, void* g_mu, void* ws,
+                             size_t ws_bytes, void* stream) {
+    if (!g_vnext || !g_q || !g_v || !g_tau || !g_mass || (b && b->max_contacts > 0 && !g_mu)) return DSIM_ERR_ARG;
+    return dispatch<ENTRY_PVJP>(b, p, q, v, tau, g_vnext, nullptr, v_next, lam, mode, status, g_q, g_v, g_tau,
+                                g_mass, g_mu, ws, ws_bytes, stream);
 }
 
 int32_t dsim_step_integrate(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
@@ -402,7 +413,7 @@ int32_t dsim_step_integrate(const dsim_batch* b, const dsim_params* p, const voi
                             void* stream) {
     if (!q_next) return DSIM_ERR_ARG;
     return dispatch<ENTRY_SINT>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, q_next, nullptr,
-                                nullptr, nullptr, 0, stream);
+                                nullptr, nullptr, nullptr, nullptr, 0, stream);
 }
 
 int32_t dsim_step_integrate_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
@@ -411,7 +422,7 @@ int32_t dsim_step_integrate_vjp(const dsim_batch* b, const dsim_params* p, const
                                 size_t ws_bytes, void* stream) {
     if (!a_qnext || !a_vnext || !a_q || !a_v || !g_tau) return DSIM_ERR_ARG;
     return dispatch<ENTRY_RVJP>(b, p, q, v, tau, a_vnext, a_qnext, v_next, lam, mode, status, a_q, a_v, g_tau,
-                                ws, ws_bytes, stream);
+                                nullptr, nullptr, ws, ws_bytes, stream);
 }
 
 int32_t dsim_tangent_to_ambient(const dsim_batch* b, int32_t precision, const void* q, const void* g_tangent,

@@ -147,14 +147,16 @@ DSIM_HD inline void team_max2(const Team& T, double* redv, double& a, double& b)
 enum { ST_NCP = 1, ST_RANK = 2, ST_DEGEN = 4, ST_NONFINITE = 8, ST_POLISH = 16, ST_SIZE = 32 };
 enum { BRK = 0, STK = 1, SLD = 2 };
 // entries: the step; the step and its full Jacobian; the step and its VJP;
-// the step followed by q+ = q (+) dt v+; the adjoint of that fused map
-enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4 };
+// the step followed by q+ = q (+) dt v+; the adjoint of that fused map; the
+// step, its VJP and the gradients in the body masses and friction
+// coefficients
+enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4, ENTRY_PVJP = 5 };
 // FP64 impulses handed from the step launch to the derivative launch: one
 // slot of 3 x (maximum contacts) per environment
 constexpr int kLdStride = 63;
 
 DSIM_HD inline bool entry_has_derivative(int entry) {
-    return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP;
+    return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP || entry == ENTRY_PVJP;
 }
 
 template <class R>

@@ -672,6 +672,75 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
     T.sync();
 }
 
+// Gradients of gbar . v+ in the physical parameters, after `vjp` (which
+// leaves pg = M^-1 P^T gbar, so that gbar^T dv+/dtau = dt pg^T).
+//
+// The step's residual depends on a parameter at fixed (v+, Lam) through
+// inverse dynamics or through the sliding cone, never through both, so
+// each gradient is a generalised force paired with dt pg:
+//  * mass m_b (centre of mass and rotational inertia about it fixed):
+//    dID/dm_b = S^T (I' A_b + V_b x* I' V_b) over the dofs that move b,
+//    I' the unit point mass at the centre of mass, A_b and V_b the body's
+//    acceleration (gravity included) and velocity at a+; the gradient is
+//    -(V_b(dt pg)) . (I' A_b + V_b x* I' V_b), V_b(x) the body velocity for
+//    joint velocities x.
+//  * friction coefficient mu_c of a sliding contact: the tangential rows
+//    Lam_T + mu Lam_N u = 0 change like a tangential impulse -Lam_N u dmu
+//    applied outside the mode equations, i.e. a generalised force
+//    -J_c^T (Lam_N u, 0) / dt; the gradient is -Lam_N u . (J_c pg)_T.  It
+//    is zero for breaking and sticking contacts.
+template <class R>
+DSIM_HD void param_grads(const Team& T, Env<R>& E, const Params& P, R* g_mass, R* g_mu) {
+    const int n = E.nv;
+    const double* pg = E.af;
+    for (int b = T.tid; b < E.nb; b += T.nt) {
+        const double* I = E.Iw + 10 * b;
+        const double c[3] = {I[1] / I[0], I[2] / I[0], I[3] / I[0]};
+        const double Ip[10] = {1.0, c[0], c[1], c[2], c[1] * c[1] + c[2] * c[2], c[0] * c[0] + c[2] * c[2],
+                               c[0] * c[0] + c[1] * c[1], -c[0] * c[1], -c[0] * c[2], -c[1] * c[2]};
+        double f[6], iv[6], vxiv[6];
+        iapply(Ip, E.Acc + 6 * b, f);
+        iapply(Ip, E.V + 6 * b, iv);
+        mxf(E.V + 6 * b, iv, vxiv);
+        double w[6] = {0, 0, 0, 0, 0, 0};
+        const uint64_t mask = E.bmask[b];
+        for (int j = 0; j < n; ++j)
+            if ((mask >> j) & 1ull)
+                for (int a = 0; a < 6; ++a) w[a] += E.S[6 * j + a] * pg[j];
+        double s = 0;
+        for (int a = 0; a < 6; ++a) s += w[a] * (f[a] + vxiv[a]);
+        g_mass[E.b0 + b] = R(-P.dt * s);
+    }
+    for (int c = T.tid; c < E.nc; c += T.nt) {
+        double g = 0;
+        if (E.cmode[c] == SLD) {
+            const double s0 = E.dsig[3 * c], s1 = E.dsig[3 * c + 1];
+            const double ns = sqrt(s0 * s0 + s1 * s1);
+            double u0 = 1.0, u1 = 0.0;
+            if (ns > 0) {
+                u0 = s0 / ns;
+                u1 = s1 / ns;
+            } else {
+                // no slip yet: the slip direction is opposite the friction
+                const double l0 = E.Ld[3 * c], l1 = E.Ld[3 * c + 1];
+                const double nl = sqrt(l0 * l0 + l1 * l1);
+                if (nl > 0) {
+                    u0 = -l0 / nl;
+                    u1 = -l1 / nl;
+                }
+            }
+            double j0 = 0, j1 = 0;
+            for (int j = 0; j < n; ++j) {
+                j0 += double(E.J[(3 * c) * n + j]) * pg[j];
+                j1 += double(E.J[(3 * c + 1) * n + j]) * pg[j];
+            }
+            g = -E.Ld[3 * c + 2] * (u0 * j0 + u1 * j1);
+        }
+        g_mu[E.c0 + c] = R(g);
+    }
+    T.sync();
+}
+
 // Full pipeline of one environment.
 //
 // The step entries (STEP, SINT) solve the step and write its outputs, and
@@ -681,7 +750,7 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
 template <class R>
 DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, int entry, int e,
                      const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
-                     int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, double* ld) {
+                     int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, R* o4, R* o5, double* ld) {
     load_env(T, E, B, e, q, v, tau);
     if (!entry_has_derivative(entry)) {
         step_forward(T, E, B, P, q);
@@ -696,6 +765,10 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
         if (entry == ENTRY_JAC) jacobian(T, E, B, P, o1, o2, o3);
         if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
         if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
+        if (entry == ENTRY_PVJP) {
+            vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
+            param_grads(T, E, P, o4, o5);
+        }
     }
     T.sync();
 }

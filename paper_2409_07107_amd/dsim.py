@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdsim.so")
 
 F64, F32 = 0, 1
 ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP, ENTRY_STEP_INTEGRATE, ENTRY_STEP_INTEGRATE_VJP = 0, 1, 2, 3, 4
+ENTRY_VJP_PARAMS = 5
 ST_NCP_NOT_CONVERGED, ST_RANK_DEFICIENT, ST_MODE_DEGENERATE, ST_NONFINITE, ST_POLISH_FAILED = 1, 2, 4, 8, 16
 ST_SIZE_EXCEEDED = 32
 MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
@@ -25,7 +26,7 @@ MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
 SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim_validate_host",
            "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
-           "dsim_tangent_to_ambient", "dsim_struct_size")
+           "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params")
 
 _vp = ctypes.c_void_p
 
@@ -81,6 +82,9 @@ def lib():
         L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp.restype = ctypes.c_int32
+        L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_vjp_params.restype = ctypes.c_int32
         L.dsim_step_integrate.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + [_vp]
         L.dsim_step_integrate.restype = ctypes.c_int32
         L.dsim_step_integrate_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
@@ -299,6 +303,30 @@ def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | No
                                _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]), _ptr(out["g_tau"]),
                                _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_vjp_params(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None,
+                    cb=None):
+    """step_vjp plus "g_mass" (per body) and "g_mu" (per contact): g^T dv+
+    with respect to the body masses and friction coefficients."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        for k in ("g_q", "g_v", "g_tau"):
+            out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
+        out["g_mass"] = torch.empty(int(db.batch.body_off[-1]), dtype=db.dtype, device=db.device)
+        out["g_mu"] = torch.empty(max(int(db.batch.contact_off[-1]), 1), dtype=db.dtype, device=db.device)
+    ws, nbytes = db.workspace(p, ENTRY_VJP_PARAMS)
+    _check(lib().dsim_step_vjp_params(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v),
+                                      _ptr(tau), _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                      _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]),
+                                      _ptr(out["g_tau"]), _ptr(out["g_mass"]), _ptr(out["g_mu"]), _ptr(ws),
+                                      ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
     return out
 
 

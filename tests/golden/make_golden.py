@@ -7,7 +7,9 @@ nothing here comes from the HIP path.
 Each file holds, per listed environment: index, v+ (n_v), J^T Lam (n_v),
 modes (n_c), margin, solver ok flag, uniqueness of the v+ derivative, and the
 full Jacobian d v+ / d(dq, v, tau) (n_v x 3 n_v), and the NCP data (G, g,
-mu) so that a different but valid GPU solution can be recognised.
+mu) so that a different but valid GPU solution can be recognised.  The
+parameter sets hold the derivatives of v+ in the body masses and friction
+coefficients (n_v x (n_b + n_c)) instead of the Jacobian.
 """
 from __future__ import annotations
 
@@ -43,7 +45,58 @@ ROLLOUTS = {
     "rollout_tree36": ("tree36", 3, 22, 4, 0, {}),
 }
 
+# physical-parameter derivatives: name -> (workload, n_env, seed, env indices)
+PARAMS = {
+    "params_cube8": ("cube_nospin", 8, 31, list(range(8))),
+    "params_arm7": ("arm7", 64, 32, list(range(24))),
+    "params_pressed8": ("pressed", 8, 33, list(range(8))),
+    "params_tree36_16384_sample": ("tree36", 16384, 0, [0, 1, 2, 255, 256, 8191, 8192, 16382, 16383]),
+    "params_mixed_8192_sample": ("mixed", 8192, 0, [0, 1, 2, 3, 2048, 4095, 8190, 8191]),
+}
+
 _BATCH = None
+
+
+def params_inputs(name):
+    """The seeded batch of a parameter set (inputs only; shared with the GPU
+    test): a sliding cube without spin (a determinate contact problem), and
+    single pressed bodies in gap mode 1 with Baumgarte gains."""
+    wl, n, seed, envs = PARAMS[name]
+    if wl == "cube_nospin":
+        batch = scenes.cube(n, seed=seed, v_std=0.2)
+        v = batch.v.reshape(n, 6)
+        v[:, 3:] = 0.0
+        v[:, 2] = -0.05
+    elif wl == "pressed":
+        from tests.gap_scenes import pressed_bodies
+        batch = pressed_bodies(n, seed=seed, kp=0.3, kd=0.2)
+    else:
+        batch = scenes.make(wl, n, seed=seed)
+    return batch, envs
+
+
+def _param_one(e):
+    env = _BATCH.env(e)
+    r = step.forward(env)
+    d = derivative.param_ift(env, r)
+    return dict(env=e, vnext=r["vnext"], modes=np.array(r["modes"], dtype=np.int8), G=r["G"], g=r["g"],
+                mu=r["model"].mu, margin=r["margin"], ok=bool(r["info"]["ok"]), unique=bool(d["unique_v"]),
+                pjac=d["jac"])
+
+
+def make_params(name):
+    global _BATCH
+    _BATCH, envs = params_inputs(name)
+    with Pool(min(8, len(envs))) as p:
+        res = p.map(_param_one, envs)
+    out = dict(envs=np.array(envs), name=name, ragged=True)
+    for key in ("vnext", "modes", "pjac", "G", "g", "mu"):
+        for i, r in enumerate(res):
+            out[f"{key}__{i}"] = np.asarray(r[key])
+    for key in ("margin", "ok", "unique"):
+        out[key] = np.array([r[key] for r in res])
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), **out)
+    print(name, "ok", int(out["ok"].sum()), "/", len(envs), "unique", int(out["unique"].sum()), flush=True)
 
 
 def _one(e):
@@ -113,8 +166,10 @@ def make_rollout(name):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(SETS) + list(ROLLOUTS)):
+    for name in (sys.argv[1:] or list(SETS) + list(ROLLOUTS) + list(PARAMS)):
         if name in ROLLOUTS:
             make_rollout(name)
+        elif name in PARAMS:
+            make_params(name)
         else:
             make(name)
