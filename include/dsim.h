@@ -89,7 +89,8 @@ typedef enum {
     DSIM_ENTRY_VJP = 2,
     DSIM_ENTRY_STEP_INTEGRATE = 3,
     DSIM_ENTRY_STEP_INTEGRATE_VJP = 4,
-    DSIM_ENTRY_VJP_PARAMS = 5
+    DSIM_ENTRY_VJP_PARAMS = 5,
+    DSIM_ENTRY_JACOBIAN_PARAMS = 6
 } dsim_entry;
 
 /*
@@ -122,6 +123,9 @@ typedef enum {
  *   environments: this is how a ragged batch is split into size classes
  *   (each launch sized for its class) and how expensive environments are
  *   started first.
+ * pjac_off (device, n_env + 1 entries, optional): the prefix sum of
+ *   n_v (n_b + n_c), the offsets of the per-environment parameter Jacobians
+ *   of dsim_step_jacobian_params (may be NULL otherwise).
  * The max_* fields must bound every processed environment (they size the
  * on-chip buffers); n_env may be 0.
  */
@@ -133,6 +137,7 @@ typedef struct dsim_batch {
     const void *axis, *jrot, *jpos, *mass, *com, *inertia, *cpoint, *mu;
     int32_t n_order;
     const int32_t* order;
+    const int32_t* pjac_off;
 } dsim_batch;
 
 typedef struct dsim_params {
@@ -247,6 +252,22 @@ int32_t dsim_step_vjp_params(const dsim_batch* batch, const dsim_params* params,
                              void* v_next, void* lam, int8_t* mode, int32_t* status,
                              void* g_q, void* g_v, void* g_tau, void* g_mass, void* g_mu,
                              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Forward mode in the physical parameters: everything dsim_step_jacobian
+ * computes, plus dvdp, per environment an n_v x (n_b + n_c) row-major block
+ * at pjac_off[e]: column b < n_b is d v+ / d m_b (body mass, centre of mass
+ * and rotational inertia about it fixed), column n_b + c is d v+ / d mu_c
+ * (zero unless contact c slides).  The columns are extra right-hand sides of
+ * the same reduced system (formed as Q times a generalised force, Q = P M^-1
+ * of the Jacobian assembly).  Requires batch->jac_off and batch->pjac_off.
+ * Workspace and errors: as dsim_step_jacobian.
+ */
+int32_t dsim_step_jacobian_params(const dsim_batch* batch, const dsim_params* params,
+                                  const void* q, const void* v, const void* tau,
+                                  void* v_next, void* lam, int8_t* mode, int32_t* status,
+                                  void* dvdq, void* dvdv, void* dvdtau, void* dvdp,
+                                  void* ws, size_t ws_bytes, void* stream);
 
 /*
  * The step followed by the position update q_next = q (+) dt v_next

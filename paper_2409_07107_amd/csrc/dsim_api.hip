@@ -38,6 +38,7 @@ BatchView<R> view(const dsim_batch* b) {
     v.cpoint = static_cast<const R*>(b->cpoint);
     v.mu = static_cast<const R*>(b->mu);
     v.order = b->order;
+    v.pjac_off = b->pjac_off;
     return v;
 }
 
@@ -389,6 +390,16 @@ int32_t dsim_step_jacobian(const dsim_batch* b, const dsim_params* p, const void
     if (!dvdq || !dvdv || !dvdtau || (b && b->n_env > 0 && !b->jac_off)) return DSIM_ERR_ARG;
     return dispatch<ENTRY_JAC>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, dvdq, dvdv, dvdtau,
                                nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int32_t dsim_step_jacobian_params(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                                  const void* tau, void* v_next, void* lam, int8_t* mode, int32_t* status,
+                                  void* dvdq, void* dvdv, void* dvdtau, void* dvdp, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    if (!dvdq || !dvdv || !dvdtau || !dvdp || (b && b->n_env > 0 && (!b->jac_off || !b->pjac_off)))
+        return DSIM_ERR_ARG;
+    return dispatch<ENTRY_PJAC>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, dvdq, dvdv, dvdtau,
+                                dvdp, nullptr, ws, ws_bytes, stream);
 }
 
 int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,

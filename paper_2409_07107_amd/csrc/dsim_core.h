@@ -149,15 +149,18 @@ enum { BRK = 0, STK = 1, SLD = 2 };
 // entries: the step; the step and its full Jacobian; the step and its VJP;
 // the step followed by q+ = q (+) dt v+; the adjoint of that fused map; the
 // step, its VJP and the gradients in the body masses and friction
-// coefficients
-enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4, ENTRY_PVJP = 5 };
+// coefficients; the step, its Jacobian and the parameter columns
+enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4, ENTRY_PVJP = 5, ENTRY_PJAC = 6 };
 // FP64 impulses handed from the step launch to the derivative launch: one
 // slot of 3 x (maximum contacts) per environment
 constexpr int kLdStride = 63;
 
 DSIM_HD inline bool entry_has_derivative(int entry) {
-    return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP || entry == ENTRY_PVJP;
+    return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP || entry == ENTRY_PVJP ||
+           entry == ENTRY_PJAC;
 }
+// entries that assemble the full Jacobian (they need the T and CZ buffers)
+DSIM_HD inline bool entry_is_jacobian(int entry) { return entry == ENTRY_JAC || entry == ENTRY_PJAC; }
 
 template <class R>
 struct BatchView {
@@ -166,6 +169,7 @@ struct BatchView {
     const int32_t *parent, *jtype, *cbody;
     const R *axis, *jrot, *jpos, *mass, *com, *inertia, *cpoint, *mu;
     const int32_t* order;  // optional launch list (block index -> environment)
+    const int32_t* pjac_off;  // offsets of the parameter Jacobians
 };
 
 struct Params {
@@ -352,7 +356,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.Mi = gda;
     } else {
         const size_t mxb = size_t(NN) * sizeof(double);
-        const size_t czb = (entry == ENTRY_JAC) ? size_t(KK > NN ? KK : NN) * sizeof(R) : 0;
+        const size_t czb = entry_is_jacobian(entry) ? size_t(KK > NN ? KK : NN) * sizeof(R) : 0;
         const size_t b = mxb > czb ? mxb : czb;
         E.Mx = take<double>(p, (b + sizeof(double) - 1) / sizeof(double), tot);
         E.Mi = take<double>(p, NN, tot);
@@ -419,7 +423,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.dTv = take<R>(p, NN, tot);
         E.E = take<R>(p, K * NV, tot);
         E.Z = E.Gd;
-        if (entry == ENTRY_JAC)
+        if (entry_is_jacobian(entry))
             E.T = (size_t(NV) * K * sizeof(R) <= size_t(KK) * sizeof(double)) ? reinterpret_cast<R*>(E.Gd)
                                                                                 : take<R>(p, NV * K, tot);
         else

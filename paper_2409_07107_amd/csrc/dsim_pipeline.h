@@ -741,6 +741,62 @@ DSIM_HD void param_grads(const Team& T, Env<R>& E, const Params& P, R* g_mass, R
     T.sync();
 }
 
+// Forward-mode columns of the physical parameters, after `jacobian` (Q =
+// P M^-1 is still formed): with the generalised forces of `param_grads`,
+//   d v+ / d m_b  = -dt Q S^T (I' A_b + V_b x* I' V_b)   (dofs that move b)
+//   d v+ / d mu_c = -Q J_c^T (Lam_N u, 0)                  (sliding contacts)
+// written row-major n x (n_b + n_c) at pjac_off[e].  Each thread forms the
+// generalised force of its column on the fly (no scratch).
+template <class R>
+DSIM_HD void param_columns(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, R* dvdp) {
+    const int n = E.nv, nb = E.nb, nc = E.nc, np = nb + nc;
+    const int off = B.pjac_off[E.e];
+    for (int idx = T.tid; idx < n * np; idx += T.nt) {
+        const int i = idx / np, col = idx - i * np;
+        double s = 0;
+        if (col < nb) {
+            const int b = col;
+            const double* I = E.Iw + 10 * b;
+            const double c[3] = {I[1] / I[0], I[2] / I[0], I[3] / I[0]};
+            const double Ip[10] = {1.0, c[0], c[1], c[2], c[1] * c[1] + c[2] * c[2], c[0] * c[0] + c[2] * c[2],
+                                   c[0] * c[0] + c[1] * c[1], -c[0] * c[1], -c[0] * c[2], -c[1] * c[2]};
+            double f[6], iv[6], vxiv[6];
+            iapply(Ip, E.Acc + 6 * b, f);
+            iapply(Ip, E.V + 6 * b, iv);
+            mxf(E.V + 6 * b, iv, vxiv);
+            for (int a = 0; a < 6; ++a) f[a] += vxiv[a];
+            const uint64_t mask = E.bmask[b];
+            for (int l = 0; l < n; ++l)
+                if ((mask >> l) & 1ull) s += double(E.Q[i * n + l]) * dot6(E.S + 6 * l, f);
+            s *= -P.dt;
+        } else {
+            const int cc = col - nb;
+            if (E.cmode[cc] == SLD) {
+                const double s0 = E.dsig[3 * cc], s1 = E.dsig[3 * cc + 1];
+                const double ns = sqrt(s0 * s0 + s1 * s1);
+                double u0 = 1.0, u1 = 0.0;
+                if (ns > 0) {
+                    u0 = s0 / ns;
+                    u1 = s1 / ns;
+                } else {
+                    const double l0 = E.Ld[3 * cc], l1 = E.Ld[3 * cc + 1];
+                    const double nl = sqrt(l0 * l0 + l1 * l1);
+                    if (nl > 0) {
+                        u0 = -l0 / nl;
+                        u1 = -l1 / nl;
+                    }
+                }
+                for (int l = 0; l < n; ++l)
+                    s += double(E.Q[i * n + l]) *
+                         (u0 * double(E.J[(3 * cc) * n + l]) + u1 * double(E.J[(3 * cc + 1) * n + l]));
+                s *= -E.Ld[3 * cc + 2];
+            }
+        }
+        dvdp[off + idx] = R(s);
+    }
+    T.sync();
+}
+
 // Full pipeline of one environment.
 //
 // The step entries (STEP, SINT) solve the step and write its outputs, and
@@ -763,6 +819,10 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
     } else {
         restore_step(T, E, B, P, q, ld, mode);
         if (entry == ENTRY_JAC) jacobian(T, E, B, P, o1, o2, o3);
+        if (entry == ENTRY_PJAC) {
+            jacobian(T, E, B, P, o1, o2, o3);
+            param_columns(T, E, B, P, o4);
+        }
         if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
         if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
         if (entry == ENTRY_PVJP) {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdsim.so")
 
 F64, F32 = 0, 1
 ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP, ENTRY_STEP_INTEGRATE, ENTRY_STEP_INTEGRATE_VJP = 0, 1, 2, 3, 4
-ENTRY_VJP_PARAMS = 5
+ENTRY_VJP_PARAMS, ENTRY_JACOBIAN_PARAMS = 5, 6
 ST_NCP_NOT_CONVERGED, ST_RANK_DEFICIENT, ST_MODE_DEGENERATE, ST_NONFINITE, ST_POLISH_FAILED = 1, 2, 4, 8, 16
 ST_SIZE_EXCEEDED = 32
 MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
@@ -26,7 +26,8 @@ MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
 SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim_validate_host",
            "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
-           "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params")
+           "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params",
+           "dsim_step_jacobian_params")
 
 _vp = ctypes.c_void_p
 
@@ -37,7 +38,7 @@ class CBatch(ctypes.Structure):
                 ("body_off", _vp), ("dof_off", _vp), ("cfg_off", _vp), ("contact_off", _vp), ("jac_off", _vp),
                 ("parent", _vp), ("jtype", _vp), ("cbody", _vp),
                 ("axis", _vp), ("jrot", _vp), ("jpos", _vp), ("mass", _vp), ("com", _vp), ("inertia", _vp),
-                ("cpoint", _vp), ("mu", _vp), ("n_order", ctypes.c_int32), ("order", _vp)]
+                ("cpoint", _vp), ("mu", _vp), ("n_order", ctypes.c_int32), ("order", _vp), ("pjac_off", _vp)]
 
 
 class CParams(ctypes.Structure):
@@ -85,6 +86,9 @@ def lib():
         L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp_params.restype = ctypes.c_int32
+        L.dsim_step_jacobian_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_jacobian_params.restype = ctypes.c_int32
         L.dsim_step_integrate.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + [_vp]
         L.dsim_step_integrate.restype = ctypes.c_int32
         L.dsim_step_integrate_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
@@ -115,6 +119,17 @@ def params(prec=F32, **overrides) -> CParams:
         else:
             setattr(p, k, type(getattr(p, k))(v))
     return p
+
+
+def param_jac_offsets(batch) -> np.ndarray:
+    """Prefix sum of n_v (n_b + n_c): offsets of the parameter Jacobians."""
+    nv = np.diff(np.asarray(batch.dof_off, dtype=np.int64))
+    npar = np.diff(np.asarray(batch.body_off, dtype=np.int64)) + np.diff(np.asarray(batch.contact_off, dtype=np.int64))
+    o = np.zeros(len(nv) + 1, dtype=np.int64)
+    o[1:] = np.cumsum(nv * npar)
+    if o[-1] >= 2 ** 31:
+        raise ValueError("parameter Jacobian offsets exceed int32")
+    return o.astype(np.int32)
 
 
 def jac_offsets(dof_off) -> np.ndarray:
@@ -171,6 +186,7 @@ class DeviceBatch:
         self.arrays = dict(
             body_off=t(batch.body_off, i32), dof_off=t(batch.dof_off, i32), cfg_off=t(batch.cfg_off, i32),
             contact_off=t(batch.contact_off, i32), jac_off=t(jac_offsets(batch.dof_off), i32),
+            pjac_off=t(param_jac_offsets(batch), i32),
             parent=t(batch.parent, i32), jtype=t(batch.jtype, i32),
             cbody=t(batch.cbody if len(batch.cbody) else np.zeros(1), i32),
             axis=t(batch.axis, R), jrot=t(batch.jrot, R), jpos=t(batch.jpos, R), mass=t(batch.mass, R),
@@ -186,6 +202,8 @@ class DeviceBatch:
                         *(a[k].data_ptr() for k in ("body_off", "dof_off", "cfg_off", "contact_off", "jac_off",
                                                     "parent", "jtype", "cbody", "axis", "jrot", "jpos", "mass",
                                                     "com", "inertia", "cpoint", "mu")))
+        self.c.pjac_off = a["pjac_off"].data_ptr()
+        self.n_pjac = int(param_jac_offsets(batch)[-1])
         self.n_env = batch.n_env
         self.n_dof = int(batch.dof_off[-1])
         self.n_contact = int(batch.contact_off[-1])
@@ -327,6 +345,29 @@ def step_vjp_params(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CPara
                                       _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]),
                                       _ptr(out["g_tau"]), _ptr(out["g_mass"]), _ptr(out["g_mu"]), _ptr(ws),
                                       ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_jacobian_params(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
+    """step_jacobian plus "dvdp": per environment the n_v x (n_b + n_c)
+    derivative of v+ in the body masses and friction coefficients, at
+    param_jac_offsets(batch)."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        for k in ("dvdq", "dvdv", "dvdtau"):
+            out[k] = torch.empty(max(db.n_jac, 1), dtype=db.dtype, device=db.device)
+        out["dvdp"] = torch.empty(max(db.n_pjac, 1), dtype=db.dtype, device=db.device)
+    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN_PARAMS)
+    _check(lib().dsim_step_jacobian_params(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q),
+                                           _ptr(v), _ptr(tau), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                           _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["dvdq"]),
+                                           _ptr(out["dvdv"]), _ptr(out["dvdtau"]), _ptr(out["dvdp"]), _ptr(ws),
+                                           ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
     return out
 
 

@@ -118,6 +118,7 @@ def test_null_arguments_are_rejected(L):
     assert L.dsim_step(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), None, 0, None) == -1
     assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([None] * 10), None, 0, None) == -1
     assert L.dsim_step_vjp_params(ctypes.byref(cb), ctypes.byref(p), *([None] * 13), None, 0, None) == -1
+    assert L.dsim_step_jacobian_params(ctypes.byref(cb), ctypes.byref(p), *([None] * 11), None, 0, None) == -1
 
 
 def test_on_chip_sizing(L):
@@ -135,7 +136,8 @@ def test_on_chip_sizing(L):
         assert step <= 160 * 1024 // (3 if prec == dsim.F32 else 2)
         # the derivative entries hand 63 FP64 impulses per environment over
         # from their step launch; the step entries need no workspace
-        for entry in (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP, dsim.ENTRY_STEP_INTEGRATE_VJP, dsim.ENTRY_VJP_PARAMS):
+        for entry in (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP, dsim.ENTRY_STEP_INTEGRATE_VJP, dsim.ENTRY_VJP_PARAMS,
+                      dsim.ENTRY_JACOBIAN_PARAMS):
             assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 504 * b.n_env
         for entry in (dsim.ENTRY_STEP, dsim.ENTRY_STEP_INTEGRATE):
             assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 0
