@@ -150,3 +150,36 @@ def test_param_columns_agree_with_the_reverse_mode(precision, gpu_lib):
         ref = g[d0:d1] @ blk
         got = np.concatenate([gm[b0:b1], gmu[c0:c1]])
         assert np.linalg.norm(got - ref) <= tol * max(np.linalg.norm(ref), 1e-8), e
+
+
+def test_autograd_in_the_physical_parameters(gpu_lib):
+    """DiffStepParams: the mass and friction tensors replace the batch's
+    tables (a changed mass gives the step of a batch built with it) and
+    autograd returns the library's parameter gradients."""
+    import copy
+    import torch
+    from paper_2409_07107_amd import dsim, scenes
+    from paper_2409_07107_amd.autograd import diff_step_params
+    batch = scenes.make("arm7", 16, seed=8)
+    db = dsim.DeviceBatch(batch, precision=0)
+    mass = db.arrays["mass"].clone().requires_grad_(True)
+    mu = db.arrays["mu"].clone().requires_grad_(True)
+    w = torch.as_tensor(np.random.default_rng(4).normal(size=db.n_dof), dtype=db.dtype, device=db.device)
+    vn, _ = diff_step_params(db, db.q, db.v, db.tau, mass, mu)
+    (vn * w).sum().backward()
+    ref = dsim.step_vjp_params(db, w)
+    torch.cuda.synchronize()
+    assert torch.equal(vn, ref["v_next"])
+    assert torch.equal(mass.grad, ref["g_mass"])
+    assert torch.equal(mu.grad[:db.n_contact], ref["g_mu"][:db.n_contact])
+    # a heavier first link and a different friction table
+    b2 = copy.deepcopy(batch)
+    b2.mass = np.array(batch.mass, dtype=np.float64)
+    b2.mu = np.array(batch.mu, dtype=np.float64)
+    b2.mass[batch.body_off[3]] *= 1.5
+    b2.mu[:] = np.linspace(0.2, 1.0, len(b2.mu))
+    db2 = dsim.DeviceBatch(b2, precision=0)
+    vn2, _ = diff_step_params(db, db.q, db.v, db.tau, db2.arrays["mass"], db2.arrays["mu"])
+    ref2 = dsim.step(db2)
+    torch.cuda.synchronize()
+    assert torch.equal(vn2, ref2["v_next"])
