@@ -136,6 +136,11 @@ class Model:
         self.cbody = [int(b) for b in env["cbody"]]
         self.nc = len(self.cbody)
         self.cpoint = t64(env["cpoint"]).reshape(self.nc, 3)
+        # sphere contacts: radius r > 0 means a sphere centred at cpoint that
+        # touches the plane z = 0 at its lowest point (primitive-plane
+        # collision, Appendix C); r = 0 is the body-fixed point itself
+        self.cradius = t64(env.get("cradius", np.zeros(self.nc))).reshape(self.nc)
+        self.ez = torch.tensor([0.0, 0.0, 1.0], dtype=F64)
         self.mu = np.asarray(env["mu"], dtype=np.float64).reshape(self.nc)
         self.dt = float(env["dt"])
         self.gravity = t64(env["gravity"]).reshape(3)
@@ -270,7 +275,7 @@ class Model:
             for c in range(self.nc):
                 i = self.cbody[c]
                 fb = Rw[i].T @ fext_world[c]
-                x = self.cpoint[c]
+                x = self.contact_point_body(c, Rw[i])
                 frc[i] = frc[i] - torch.cat([torch.linalg.cross(x, fb), fb])
         tau = [None] * self.nb
         for i in reversed(range(self.nb)):
@@ -301,6 +306,13 @@ class Model:
             vel.append(self._motion_to_child(R, p, vp) + sv)
         return vel, Rw, pw
 
+    def contact_point_body(self, c, Rw):
+        """The contact point of contact c in its body's frame, given the
+        body's world rotation: the lowest point of the sphere, centre minus
+        r times the plane normal expressed in the body frame (it moves
+        through the body as the body turns)."""
+        return self.cpoint[c] - self.cradius[c] * (Rw.T @ self.ez)
+
     def contact_velocity(self, q, v, dq=None):
         """World velocities of the contact points, stacked (T1 T2 N) = (x y z):
         the forward-kinematics velocity FKV(q, v, c) of Appendix D."""
@@ -309,14 +321,15 @@ class Model:
         for c in range(self.nc):
             i = self.cbody[c]
             w, lin = vel[i][:3], vel[i][3:]
-            out.append(Rw[i] @ (lin + torch.linalg.cross(w, self.cpoint[c])))
+            out.append(Rw[i] @ (lin + torch.linalg.cross(w, self.contact_point_body(c, Rw[i]))))
         if not out:
             return torch.zeros(0, dtype=F64)
         return torch.cat(out)
 
     def contact_positions(self, q, dq=None):
         Rs, ps = self.forward_kinematics(q, dq)
-        out = [ps[self.cbody[c]] + Rs[self.cbody[c]] @ self.cpoint[c] for c in range(self.nc)]
+        out = [ps[self.cbody[c]] + Rs[self.cbody[c]] @ self.cpoint[c] - self.cradius[c] * self.ez
+               for c in range(self.nc)]
         if not out:
             return torch.zeros((0, 3), dtype=F64)
         return torch.stack(out)

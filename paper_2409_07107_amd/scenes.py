@@ -12,7 +12,9 @@ Batch layout (flattened over environments, ragged via prefix offsets):
                frame), jrot[3][3] + jpos[3] (joint frame placement in the
                parent body frame, rotation row-major), mass, com[3] (body
                frame), inertia[6] (about the COM, body frame: xx yy zz xy xz yz)
-  per contact: cbody (local body index), cpoint[3] (body frame), mu
+  per contact: cbody (local body index), cpoint[3] (body frame), mu, cradius
+  (0: the body-fixed point cpoint touches the plane; r > 0: a sphere of
+  radius r centred at cpoint, touching at its lowest point)
   state      : q (n_q per env), v and tau (n_v per env)
 
 Conventions: bodies are listed parents-first; a body's joint owns consecutive
@@ -69,6 +71,11 @@ class Batch:
     kd: float = 0.0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    cradius: np.ndarray = None  # per contact; None = all zero
+
+    def __post_init__(self):
+        if self.cradius is None:
+            self.cradius = np.zeros(len(self.cbody), dtype=np.float64)
 
     # ---- per-env views -------------------------------------------------
     def env(self, e: int) -> dict:
@@ -81,6 +88,7 @@ class Batch:
             axis=self.axis[b0:b1], jrot=self.jrot[b0:b1], jpos=self.jpos[b0:b1],
             mass=self.mass[b0:b1], com=self.com[b0:b1], inertia=self.inertia[b0:b1],
             cbody=self.cbody[c0:c1], cpoint=self.cpoint[c0:c1], mu=self.mu[c0:c1],
+            cradius=self.cradius[c0:c1],
             q=self.q[q0:q1], v=self.v[d0:d1], tau=self.tau[d0:d1],
             dt=self.dt, gravity=np.asarray(self.gravity, dtype=np.float64),
             gap_mode=self.gap_mode, kp=self.kp, kd=self.kd,
@@ -126,7 +134,8 @@ def _assemble(records, dt, gravity, gap_mode, name="") -> Batch:
         return o
 
     def cat(key, shape, dtype=np.float64):
-        arrs = [np.asarray(r[key], dtype=dtype).reshape((-1,) + shape) for r in records]
+        arrs = [np.asarray(r[key] if key in r else np.zeros(len(r["cbody"])), dtype=dtype).reshape((-1,) + shape)
+                for r in records]
         if not arrs:
             return np.zeros((0,) + shape, dtype=dtype)
         return np.ascontiguousarray(np.concatenate(arrs, axis=0))
@@ -137,6 +146,7 @@ def _assemble(records, dt, gravity, gap_mode, name="") -> Batch:
         axis=cat("axis", (3,)), jrot=cat("jrot", (3, 3)), jpos=cat("jpos", (3,)),
         mass=cat("mass", ()), com=cat("com", (3,)), inertia=cat("inertia", (6,)),
         cbody=cat("cbody", (), np.int32), cpoint=cat("cpoint", (3,)), mu=cat("mu", ()),
+        cradius=cat("cradius", ()),
         q=cat("q", ()), v=cat("v", ()), tau=cat("tau", ()),
         dt=float(dt), gravity=tuple(float(g) for g in gravity), gap_mode=int(gap_mode),
         name=name,
@@ -191,7 +201,7 @@ def _record(bodies, contacts, q, v, tau):
         jpos=[b["jpos"] for b in bodies], mass=[b["mass"] for b in bodies],
         com=[b["com"] for b in bodies], inertia=[b["inertia"] for b in bodies],
         cbody=[c[0] for c in contacts], cpoint=[c[1] for c in contacts],
-        mu=[c[2] for c in contacts], q=q, v=v, tau=tau,
+        mu=[c[2] for c in contacts], cradius=[c[3] if len(c) > 3 else 0.0 for c in contacts], q=q, v=v, tau=tau,
     )
 
 
@@ -360,12 +370,55 @@ def body(parent, jtype, axis=(0.0, 0.0, 1.0), jrot=None, jpos=(0.0, 0.0, 0.0),
 
 
 def record(bodies, contacts, q, v, tau):
-    """One environment record for `assemble`: contacts are (body, point, mu)."""
+    """One environment record for `assemble`: contacts are (body, point, mu)
+    or (body, sphere centre, mu, radius)."""
     return _record(bodies, contacts, np.asarray(q, dtype=np.float64),
                    np.asarray(v, dtype=np.float64), np.asarray(tau, dtype=np.float64))
 
 
-WORKLOADS = {"cube": cube, "arm7": arm7, "tree36": tree36, "mixed": mixed}
+def spheres(n_env=1, seed=0, v_std=0.3, w_std=3.0):
+    """Primitive-plane contacts: half the environments are a free ball
+    (radius U(0.03, 0.15) m, mass U(0.2, 2) kg, its centre of mass off the
+    centre by up to 0.3 r) resting on the plane, the other half a 7-joint arm
+    whose last link carries a capsule (two sphere contacts at its end caps,
+    radius U(0.02, 0.06) m) placed on the plane.  Random spin makes the
+    contact point move relative to the body.  mu ~ U(0.3, 1), dt = 1e-3."""
+    rng = np.random.default_rng(seed)
+    recs = []
+    for e in range(n_env):
+        if e % 2 == 0:
+            r = rng.uniform(0.03, 0.15)
+            m = rng.uniform(0.2, 2.0)
+            off = _unit(rng) * rng.uniform(0.0, 0.3 * r)
+            I = 0.4 * m * r * r
+            b = dict(parent=-1, jtype=FREEFLYER, axis=np.array([0.0, 0.0, 1.0]), jrot=np.eye(3),
+                     jpos=np.zeros(3), mass=m, com=off, inertia=np.array([I, I, I, 0.0, 0.0, 0.0]))
+            qrot = _small_quat(rng, 1.0)
+            R = _quat_to_rot(*qrot)
+            centre = np.zeros(3)
+            z = r - (R @ centre)[2]
+            q = np.concatenate([[0.0, 0.0, z], qrot])
+            v = np.concatenate([rng.normal(scale=v_std, size=3), rng.normal(scale=w_std, size=3)])
+            v[2] = -abs(v[2])
+            recs.append(_record([b], [(0, centre, rng.uniform(0.3, 1.0), r)], q, v, np.zeros(6)))
+        else:
+            bodies, jp = [], np.zeros(3)
+            for k in range(7):
+                L = rng.uniform(0.1, 0.3)
+                bodies.append(_link(rng, k - 1, jp, L))
+                jp = np.array([0.0, 0.0, L])
+            qj = rng.normal(scale=0.5, size=7)
+            rc = rng.uniform(0.02, 0.06)
+            half = rng.uniform(0.03, 0.08)
+            mu = rng.uniform(0.3, 1.0)
+            contacts = [(6, np.array([half, 0.0, jp[2]]), mu, rc), (6, np.array([-half, 0.0, jp[2]]), mu, rc)]
+            rec = _record(bodies, contacts, qj, rng.normal(scale=0.2, size=7), rng.normal(scale=0.5, size=7))
+            recs.append(rec)
+    b = _assemble(recs, dt=1e-3, gravity=GRAVITY, gap_mode=0, name="spheres")
+    return b
+
+
+WORKLOADS = {"cube": cube, "arm7": arm7, "tree36": tree36, "mixed": mixed, "spheres": spheres}
 
 
 def make(name: str, n_env: int, seed: int = 0, **kw) -> Batch:
