@@ -113,6 +113,12 @@ typedef enum {
  *   cbody    int32, local body index
  *   cpoint   real[3], contact point in that body's frame
  *   mu       real, friction coefficient >= 0
+ *   cradius  real, >= 0 (optional array: NULL means all 0): 0 makes cpoint
+ *            a point of the body that touches the plane z = 0; r > 0 makes
+ *            it the centre of a sphere of radius r fixed in the body, which
+ *            touches the plane at its lowest point (a point that moves
+ *            through the body as the body turns: the primitive-plane
+ *            collision contribution of Appendix C enters the derivatives)
  * jac_off (n_env + 1 entries) is the prefix sum of n_v^2, the offsets of the
  * per-environment Jacobian blocks (needed by dsim_step_jacobian only; may be
  * NULL otherwise).
@@ -138,6 +144,7 @@ typedef struct dsim_batch {
     int32_t n_order;
     const int32_t* order;
     const int32_t* pjac_off;
+    const void* cradius;
 } dsim_batch;
 
 typedef struct dsim_params {

@@ -39,6 +39,7 @@ BatchView<R> view(const dsim_batch* b) {
     v.mu = static_cast<const R*>(b->mu);
     v.order = b->order;
     v.pjac_off = b->pjac_off;
+    v.cradius = static_cast<const R*>(b->cradius);
     return v;
 }
 
@@ -308,6 +309,7 @@ int32_t dsim_validate_host(const dsim_batch* b, int32_t* bad_env) {
     const double* mass = static_cast<const double*>(b->mass);
     const double* inertia = static_cast<const double*>(b->inertia);
     const double* mu = static_cast<const double*>(b->mu);
+    const double* crad = static_cast<const double*>(b->cradius);
     if (b->body_off[0] != 0 || b->dof_off[0] != 0 || b->cfg_off[0] != 0 || b->contact_off[0] != 0)
         return DSIM_ERR_ARG;
     for (int e = 0; e < b->n_env; ++e) {
@@ -362,6 +364,7 @@ int32_t dsim_validate_host(const dsim_batch* b, int32_t* bad_env) {
             if (!b->cbody || !b->cpoint || !b->mu) return fail(DSIM_ERR_ARG);
             if (b->cbody[gc] < 0 || b->cbody[gc] >= nb) return fail(DSIM_ERR_MODEL);
             if (!(mu[gc] >= 0) || !std::isfinite(mu[gc])) return fail(DSIM_ERR_MODEL);
+            if (crad && (!(crad[gc] >= 0) || !std::isfinite(crad[gc]))) return fail(DSIM_ERR_MODEL);
         }
         if (b->jac_off && b->jac_off[e + 1] - b->jac_off[e] != nv * nv) return fail(DSIM_ERR_ARG);
     }

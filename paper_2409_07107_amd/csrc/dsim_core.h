@@ -170,6 +170,7 @@ struct BatchView {
     const R *axis, *jrot, *jpos, *mass, *com, *inertia, *cpoint, *mu;
     const int32_t* order;  // optional launch list (block index -> environment)
     const int32_t* pjac_off;  // offsets of the parameter Jacobians
+    const R* cradius;         // sphere radius per contact (nullptr: all points)
 };
 
 struct Params {
@@ -265,6 +266,7 @@ struct Env {
     uint64_t* bmask;                   // per body: dofs that move it (its own and its ancestors')
     // FP64 tree quantities
     double *Rw, *pw, *S, *V, *Vp, *Acc, *Fc, *Iw, *Ic, *Bc, *Ec, *xw, *org;
+    double* crad;  // per contact: 0 for a body-fixed point, else the sphere radius
     double *v, *tau, *bias, *af, *vf, *vn, *ap, *Mx, *Mi;
     double *IcS, *BtS, *EtS, *aj, *wj, *cj, *Yq, *Yv;
     double* gint;  // adjoint of q carried through the position update
@@ -324,6 +326,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.Iw = take<double>(p, 10 * NB, tot);
     E.Ic = take<double>(p, 10 * NB, tot);
     E.xw = take<double>(p, 3 * NC, tot);
+    E.crad = take<double>(p, NC, tot);
     E.org = take<double>(p, 3, tot);
     E.v = take<double>(p, NV, tot);
     E.tau = take<double>(p, NV, tot);

@@ -147,6 +147,12 @@ DSIM_HD void composites(const Team& T, Env<R>& E, const Params& P) {
             const double f[3] = {E.Ld[3 * c] * inv, E.Ld[3 * c + 1] * inv, E.Ld[3 * c + 2] * inv};
             const double* x = E.xw + 3 * c;
             double* X = E.Ec + 18 * b;
+            // a sphere's contact point moves with its centre, not as a point
+            // of the body: turning by w moves it by w x (r n) more, so the
+            // actual moment change gains (w x r n) x f; X holds the rigid
+            // transport minus the actual change, hence the extra
+            // -(w x r n) x f = w (f . r n) - r n (f . w)  (n = e_z)
+            const double rad = E.crad[c];
             for (int mm = 0; mm < 3; ++mm) {
                 double e[3] = {0, 0, 0};
                 e[mm] = 1;
@@ -156,6 +162,10 @@ DSIM_HD void composites(const Team& T, Env<R>& E, const Params& P) {
                 for (int r = 0; r < 3; ++r) {
                     X[3 * r + mm] += xg[r];
                     X[3 * (r + 3) + mm] += gg[r];
+                }
+                if (rad != 0.0) {
+                    X[3 * mm + mm] += rad * f[2];
+                    X[3 * 2 + mm] -= rad * f[mm];
                 }
             }
         }
@@ -311,6 +321,18 @@ DSIM_HD void velocity_partials(const Team& T, Env<R>& E, const Params& P) {
             cross3(Sj, du, t1);
             cross3(wl, dx, t2);
             val = t1[r] + t2[r];
+            // a sphere's contact point moves with the centre: it is displaced
+            // by xi_ang x (r n) more than a point of the body, which the body
+            // rotation carries into the point velocity (n = e_z)
+            const double rad = E.crad[c];
+            double sn[3] = {0, 0, 0};
+            if (rad != 0.0) {
+                const double rn[3] = {0, 0, rad};
+                double ex[3];
+                cross3(Sj, rn, sn);
+                cross3(Vi, sn, ex);
+                val += ex[r];
+            }
             if (P.gap_mode == 1 && r == 2) {
                 // d/dq of phi/dt - kp [phi/dt]_- (slope 0 at phi = 0) ...
                 const double phi = x[2] + E.org[2];
@@ -330,10 +352,11 @@ DSIM_HD void velocity_partials(const Team& T, Env<R>& E, const Params& P) {
                         }
                     }
                     const double dv[3] = {vi[0] - vl[0], vi[1] - vl[1], vi[2] - vl[2]};
-                    double s1[3], s2[3];
+                    double s1[3], s2[3], s3[3];
                     cross3(Sj, dv, s1);
                     cross3(w0, dx, s2);
-                    val -= P.kd * (s1[2] + s2[2]);
+                    cross3(Wi, sn, s3);  // sphere term at v (zero for points)
+                    val -= P.kd * (s1[2] + s2[2] + s3[2]);
                 }
             }
         }

@@ -70,6 +70,7 @@ DSIM_HD void load_env(const Team& T, Env<R>& E, const BatchView<R>& B, int e, co
     for (int c = T.tid; c < E.nc; c += T.nt) {
         E.cbody[c] = B.cbody[E.c0 + c];
         E.mu[c] = B.mu[E.c0 + c];
+        E.crad[c] = B.cradius ? double(B.cradius[E.c0 + c]) : 0.0;
     }
     T.sync();
 }
@@ -196,6 +197,8 @@ DSIM_HD void kinematics(const Team& T, Env<R>& E, const BatchView<R>& B, const R
         for (int i = 0; i < 3; ++i) xl[i] = double(B.cpoint[3 * (E.c0 + c) + i]);
         mat3vec(E.Rw + 9 * b, xl, x);
         for (int i = 0; i < 3; ++i) E.xw[3 * c + i] = x[i] + E.pw[3 * b + i];
+        // a sphere touches the plane z = 0 at its lowest point
+        E.xw[3 * c + 2] -= E.crad[c];
     }
     T.sync();
     // composite inertias (children are listed after their parents)

@@ -38,7 +38,8 @@ class CBatch(ctypes.Structure):
                 ("body_off", _vp), ("dof_off", _vp), ("cfg_off", _vp), ("contact_off", _vp), ("jac_off", _vp),
                 ("parent", _vp), ("jtype", _vp), ("cbody", _vp),
                 ("axis", _vp), ("jrot", _vp), ("jpos", _vp), ("mass", _vp), ("com", _vp), ("inertia", _vp),
-                ("cpoint", _vp), ("mu", _vp), ("n_order", ctypes.c_int32), ("order", _vp), ("pjac_off", _vp)]
+                ("cpoint", _vp), ("mu", _vp), ("n_order", ctypes.c_int32), ("order", _vp), ("pjac_off", _vp),
+                ("cradius", _vp)]
 
 
 class CParams(ctypes.Structure):
@@ -154,7 +155,8 @@ def _host_batch_struct(batch, keep):
                   p(batch.parent, np.int32), p(batch.jtype, np.int32), p(batch.cbody, np.int32),
                   p(batch.axis, np.float64), p(batch.jrot, np.float64), p(batch.jpos, np.float64),
                   p(batch.mass, np.float64), p(batch.com, np.float64), p(batch.inertia, np.float64),
-                  p(batch.cpoint, np.float64), p(batch.mu, np.float64))
+                  p(batch.cpoint, np.float64), p(batch.mu, np.float64), 0, None, None,
+                  p(getattr(batch, "cradius", np.zeros(len(batch.cbody))), np.float64))
 
 
 def validate_host(batch):
@@ -192,7 +194,8 @@ class DeviceBatch:
             axis=t(batch.axis, R), jrot=t(batch.jrot, R), jpos=t(batch.jpos, R), mass=t(batch.mass, R),
             com=t(batch.com, R), inertia=t(batch.inertia, R),
             cpoint=t(batch.cpoint if len(batch.cpoint) else np.zeros((1, 3)), R),
-            mu=t(batch.mu if len(batch.mu) else np.zeros(1), R))
+            mu=t(batch.mu if len(batch.mu) else np.zeros(1), R),
+            cradius=t(batch.cradius if len(batch.cradius) else np.zeros(1), R))
         self.q = t(batch.q, R)
         self.v = t(batch.v, R)
         self.tau = t(batch.tau, R)
@@ -203,6 +206,7 @@ class DeviceBatch:
                                                     "parent", "jtype", "cbody", "axis", "jrot", "jpos", "mass",
                                                     "com", "inertia", "cpoint", "mu")))
         self.c.pjac_off = a["pjac_off"].data_ptr()
+        self.c.cradius = a["cradius"].data_ptr()
         self.n_pjac = int(param_jac_offsets(batch)[-1])
         self.n_env = batch.n_env
         self.n_dof = int(batch.dof_off[-1])

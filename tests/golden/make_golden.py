@@ -34,6 +34,9 @@ SETS = {
     "arm7_4096_sample": ("arm7", 4096, 0, [0, 1, 2, 63, 64, 1000, 2047, 2048, 3001, 4093, 4094, 4095]),
     "tree36_16384_sample": ("tree36", 16384, 0, [0, 1, 2, 3, 255, 256, 4097, 8191, 8192, 12000,
                                                    16379, 16380, 16381, 16382, 16383]),
+    # sphere contacts: free balls and arms with capsule ends (gap mode 0)
+    "spheres_64": ("spheres", 64, 41, list(range(32))),
+    "spheres_16384_sample": ("spheres", 16384, 0, [0, 1, 2, 3, 4097, 8190, 8191, 16382, 16383]),
     # ragged trees of 7..40 dof with 0..16 contacts
     "mixed_8192_sample": ("mixed", 8192, 0, [0, 1, 2, 3, 4, 5, 6, 7, 1000, 2047, 2048, 4095, 4096, 6000,
                                              8188, 8189, 8190, 8191]),
