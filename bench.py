@@ -350,6 +350,42 @@ def run_params(args):
     print(json.dumps(line), flush=True)
 
 
+def run_spheres(args):
+    """Sphere contacts: 16384 environments, half free balls (one sphere
+    contact), half 7-joint arms with a capsule end (two end-cap sphere
+    contacts), FP32, step + full Jacobian per call."""
+    import torch
+    from paper_2409_07107_amd import dsim, scenes
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    batch = scenes.make("spheres", 16384, seed=0)
+    db = dsim.DeviceBatch(batch, precision=dsim.F32)
+    p = db.params()
+    out = dsim.step_jacobian(db, p=p)
+    for _ in range(args.warmup):
+        dsim.step_jacobian(db, p=p, out=out)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(args.steps):
+        dsim.step_jacobian(db, p=p, out=out)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / args.steps
+    status = out["status"].cpu().numpy()
+    line = {
+        "metric": "step-derivative evals/sec, sphere contacts (balls and capsule-ended 7-dof arms), FP32",
+        "value": batch.n_env / (ms * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "spheres x 16384: free balls r ~ U(0.03, 0.15) m with eccentric mass and spin, "
+                               "7-joint arms with a capsule end (two end-cap spheres); step + full Jacobian",
+                   "n_env": batch.n_env, "seed": 0},
+        "flagged_envs": int(((status & 17) != 0).sum()),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def copy_probe(nbytes):
     """One plain elementwise copy kernel (dst = src * 1 in FP32) over nbytes:
     the reference reading of the HBM byte counters (FETCH_SIZE, WRITE_SIZE)
@@ -371,7 +407,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-f32", action="store_true",
                     help="time only the FP32 launch and print no JSON line (for profiler runs)")
-    ap.add_argument("--workload", choices=("tree36", "mixed", "rollout", "params"), default="tree36",
+    ap.add_argument("--workload", choices=("tree36", "mixed", "rollout", "params", "spheres"), default="tree36",
                     help="tree36 (the headline line), the ragged mixed batch, 200-step rollouts, or the reverse "
                          "mode with physical-parameter gradients")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -392,6 +428,9 @@ def main():
         return
     if args.workload == "params":
         run_params(args)
+        return
+    if args.workload == "spheres":
+        run_spheres(args)
         return
     run(args)
 
