@@ -393,7 +393,11 @@ def copy_probe(nbytes):
     import torch
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
+    # write 1 GiB elsewhere first, so that no part of src is still held in
+    # the caches (L2, and the 256 MB memory-side cache) when the copy reads it
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(2.0)
     torch.cuda.synchronize()
+    del flush
     torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
