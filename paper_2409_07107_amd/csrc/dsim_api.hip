@@ -372,7 +372,7 @@ int32_t dsim_validate_host(const dsim_batch* b, int32_t* bad_env) {
 }
 
 size_t dsim_lds_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) {
-    if (!b || !p || entry < 0 || entry > DSIM_ENTRY_STEP_INTEGRATE_VJP) return 0;
+    if (!b || !p || entry < 0 || entry > DSIM_ENTRY_JACOBIAN_PARAMS) return 0;
     return team_bytes(b, p, entry);
 }
 

@@ -141,3 +141,7 @@ def test_on_chip_sizing(L):
             assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 504 * b.n_env
         for entry in (dsim.ENTRY_STEP, dsim.ENTRY_STEP_INTEGRATE):
             assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 0
+        # the parameter entries share the on-chip layout of their plain forms
+        assert L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_JACOBIAN_PARAMS) == lds
+        assert L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_VJP_PARAMS) == \
+            L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_VJP)
