@@ -308,8 +308,9 @@ def run_rollout(args):
 def run_params(args):
     """Reverse mode in the state and the physical parameters: tree36 x 16384,
     FP32, one dsim_step_vjp_params call per step (gbar^T dv+ with respect to
-    q, v, tau, the 31 body masses and the 8 friction coefficients), timed
-    with HIP events beside dsim_step_vjp on the same batch."""
+    q, v, tau, the 31 body masses, their 6 x 31 rotational-inertia
+    components and the 8 friction coefficients), timed with HIP events
+    beside dsim_step_vjp on the same batch."""
     import torch
     from paper_2409_07107_amd import dsim, scenes
     if not torch.cuda.is_available():
@@ -337,7 +338,7 @@ def run_params(args):
     ms_v = timed(lambda: dsim.step_vjp(db, gbar, p=p, out=out_v))
     status = out_p["status"].cpu().numpy()
     line = {
-        "metric": "step VJP evals/sec with mass and friction gradients (36-dof tree, 8 contacts), FP32",
+        "metric": "step VJP evals/sec with mass, inertia and friction gradients (36-dof tree, 8 contacts), FP32",
         "value": batch.n_env / (ms_p * 1e-3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_p, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -345,7 +346,7 @@ def run_params(args):
                    "n_env": batch.n_env, "seed": 0},
         "state_vjp_only": {"ms_per_step": ms_v, "value": batch.n_env / (ms_v * 1e-3)},
         "flagged_envs": int(((status & 17) != 0).sum()),
-        "finite_gradients": bool(torch.isfinite(out_p["g_mass"]).all() and torch.isfinite(out_p["g_mu"]).all()),
+        "finite_gradients": bool(torch.isfinite(out_p["g_params"]).all()),
     }
     print(json.dumps(line), flush=True)
 

@@ -130,7 +130,7 @@ typedef enum {
  *   (each launch sized for its class) and how expensive environments are
  *   started first.
  * pjac_off (device, n_env + 1 entries, optional): the prefix sum of
- *   n_v (n_b + n_c), the offsets of the per-environment parameter Jacobians
+ *   n_v (7 n_b + n_c), the offsets of the per-environment parameter Jacobians
  *   of dsim_step_jacobian_params (may be NULL otherwise).
  * The max_* fields must bound every processed environment (they size the
  * on-chip buffers); n_env may be 0.
@@ -242,30 +242,33 @@ int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
 /*
  * Reverse mode in the physical parameters as well (derivatives with respect
  * to physical parameters, Section II.D, by the implicit differentiation of
- * the same mode system): everything dsim_step_vjp computes, plus
- *   g_mass [sum n_b]: gbar^T dv+/dm_b per body (global body index), the
- *     body's mass changing with its centre of mass and its rotational
- *     inertia about the centre of mass held fixed;
- *   g_mu [sum n_c]: gbar^T dv+/dmu_c per contact (zero for breaking and
- *     sticking contacts, whose equations do not involve mu).
- * Both are generalised forces paired with dt M^-1 P^T gbar, the vector the
+ * the same mode system): everything dsim_step_vjp computes, plus g_params
+ * [7 sum n_b + sum n_c], per environment e at 7 body_off[e] + contact_off[e]:
+ *   n_b entries gbar^T dv+/dm_b (body masses; the centre of mass and the
+ *     rotational inertia about it held fixed),
+ *   6 n_b entries gbar^T dv+/dI_b,k (rotational inertia about the centre of
+ *     mass in the body frame, components xx yy zz xy xz yz of each body in
+ *     turn, each off-diagonal component moving both symmetric entries),
+ *   n_c entries gbar^T dv+/dmu_c (zero for breaking and sticking contacts,
+ *     whose equations do not involve mu).
+ * Each is a generalised force paired with dt M^-1 P^T gbar, the vector the
  * reverse mode already forms, so the cost over dsim_step_vjp is one pass
- * over the bodies and contacts.  g_mu may be NULL only when the batch has
- * no contacts.  Workspace: as dsim_step_vjp.  Errors: as dsim_step_vjp.
+ * over the bodies and contacts.  Workspace and errors: as dsim_step_vjp.
  */
 int32_t dsim_step_vjp_params(const dsim_batch* batch, const dsim_params* params,
                              const void* q, const void* v, const void* tau,
                              const void* g_vnext,
                              void* v_next, void* lam, int8_t* mode, int32_t* status,
-                             void* g_q, void* g_v, void* g_tau, void* g_mass, void* g_mu,
+                             void* g_q, void* g_v, void* g_tau, void* g_params,
                              void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Forward mode in the physical parameters: everything dsim_step_jacobian
- * computes, plus dvdp, per environment an n_v x (n_b + n_c) row-major block
- * at pjac_off[e]: column b < n_b is d v+ / d m_b (body mass, centre of mass
- * and rotational inertia about it fixed), column n_b + c is d v+ / d mu_c
- * (zero unless contact c slides).  The columns are extra right-hand sides of
+ * computes, plus dvdp, per environment an n_v x (7 n_b + n_c) row-major
+ * block at pjac_off[e], its columns in the order of the g_params entries of
+ * dsim_step_vjp_params: n_b body masses, 6 n_b rotational inertias, n_c
+ * friction coefficients (a friction column is zero unless the contact
+ * slides).  The columns are extra right-hand sides of
  * the same reduced system (formed as Q times a generalised force, Q = P M^-1
  * of the Jacobian assembly).  Requires batch->jac_off and batch->pjac_off.
  * Workspace and errors: as dsim_step_jacobian.

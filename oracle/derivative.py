@@ -184,25 +184,35 @@ def appendix_b(env: dict, res: dict | None = None):
     return dict(jac=jac, dLam=dLam, A=A, B=B, C=C, D0=D0, E=E, rhs=rhs)
 
 
+def _icom_from(inr):
+    """(nb, 3, 3) rotational inertias from the stored xx yy zz xy xz yz."""
+    nb = inr.shape[0]
+    rows = [torch.stack([inr[:, 0], inr[:, 3], inr[:, 4]], 1),
+            torch.stack([inr[:, 3], inr[:, 1], inr[:, 5]], 1),
+            torch.stack([inr[:, 4], inr[:, 5], inr[:, 2]], 1)]
+    return torch.stack(rows, 1).reshape(nb, 3, 3)
+
+
 def _param_system(model: Model, q, v, tau, modes, gap_mode):
     """The same mode system as a function of y = (v+, Lam) and the physical
-    parameters p = (body masses, friction coefficients), with (q, v, tau)
-    fixed.  A body's mass changes with its centre of mass and its rotational
-    inertia about the centre of mass held fixed."""
+    parameters p = (body masses [nb], rotational inertias about the centres
+    of mass [6 nb, xx yy zz xy xz yz per body, body frame], friction
+    coefficients [nc]), with (q, v, tau) fixed.  A body's mass changes with
+    its centre of mass and its rotational inertia held fixed."""
     dt = model.dt
     nv, nc, nb = model.nv, model.nc, model.nb
-    base_mass = model.mass
+    base_mass, base_icom = model.mass, model.Icom
 
     def F(y, p):
         vn, Lam = y[:nv], y[nv:]
-        mass, mu = p[:nb], p[nb:]
+        mass, inr, mu = p[:nb], p[nb:7 * nb].reshape(nb, 6), p[7 * nb:]
         a = (vn - t64(v)) / dt
         fext = (Lam / dt).reshape(nc, 3) if nc else None
-        model.mass = mass
+        model.mass, model.Icom = mass, _icom_from(inr)
         try:
             Fdyn = dt * (model.rnea(t64(q), t64(v), a, fext_world=fext) - t64(tau))
         finally:
-            model.mass = base_mass
+            model.mass, model.Icom = base_mass, base_icom
         if nc == 0:
             return Fdyn
         sig = model.contact_velocity(t64(q), vn)
@@ -229,15 +239,18 @@ def _param_system(model: Model, q, v, tau, modes, gap_mode):
 
 
 def param_ift(env: dict, res: dict | None = None):
-    """dv+/d(mass, mu) by the implicit-function theorem on the raw mode
-    system (the physical-parameter columns of the same dF/dy).  Returns
-    dict(jac = (n, nb + nc), unique_v, ...): columns are the body masses,
-    then the contacts' friction coefficients."""
+    """dv+/d(mass, inertia, mu) by the implicit-function theorem on the raw
+    mode system (the physical-parameter columns of the same dF/dy).  Returns
+    dict(jac = (n, 7 nb + nc), unique_v, ...): columns are the body masses,
+    then the six rotational-inertia components of each body (xx yy zz xy xz
+    yz about the centre of mass, body frame), then the contacts' friction
+    coefficients."""
     res = res or forward(env)
     model = res["model"]
     nv = model.nv
     y0 = torch.cat([t64(res["vnext"]), t64(res["Lam"])])
-    p0 = torch.cat([model.mass.clone(), t64(model.mu)])
+    p0 = torch.cat([model.mass.clone(), t64(np.asarray(env["inertia"], dtype=np.float64).reshape(-1)),
+                    t64(model.mu)])
     F = _param_system(model, env["q"], env["v"], env["tau"], res["modes"], model.gap_mode)
     Fy, Fp = torch.autograd.functional.jacobian(F, (y0, p0))
     Fy, Fp = Fy.numpy(), Fp.numpy()
@@ -251,31 +264,41 @@ def param_ift(env: dict, res: dict | None = None):
 
 
 def param_finite_differences(env: dict, res: dict | None = None, h=1e-6):
-    """Central differences of v+ in the body masses and the friction
-    coefficients (relative steps h * value); returns (jac, valid) with valid
+    """Central differences of v+ in the body masses, rotational inertias and
+    friction coefficients (relative steps h * value, inertia steps h times
+    the body's largest principal moment); returns (jac, valid) with valid
     False where a perturbed step changes a contact mode."""
     res = res or forward(env)
     model = res["model"]
     nb, nc, nv = model.nb, model.nc, model.nv
     mass = np.asarray(env["mass"], dtype=np.float64)
+    inr = np.asarray(env["inertia"], dtype=np.float64).reshape(nb, 6)
     mu = np.asarray(env["mu"], dtype=np.float64)
-    jac = np.full((nv, nb + nc), np.nan)
-    valid = np.zeros(nb + nc, dtype=bool)
+    ncol = 7 * nb + nc
+    jac = np.full((nv, ncol), np.nan)
+    valid = np.zeros(ncol, dtype=bool)
     base_modes = list(res["modes"])
-    for col in range(nb + nc):
+    for col in range(ncol):
         outs, same = [], True
         if col < nb:
             step = h * mass[col]
+        elif col < 7 * nb:
+            b = (col - nb) // 6
+            step = h * np.abs(inr[b, :3]).max()
         else:
-            step = h * max(mu[col - nb], 1e-3)
+            step = h * max(mu[col - 7 * nb], 1e-3)
         for sgn in (1.0, -1.0):
             e = dict(env)
             e["mass"] = mass.copy()
+            e["inertia"] = inr.copy()
             e["mu"] = mu.copy()
             if col < nb:
                 e["mass"][col] += sgn * step
+            elif col < 7 * nb:
+                b, k = divmod(col - nb, 6)
+                e["inertia"][b, k] += sgn * step
             else:
-                e["mu"][col - nb] += sgn * step
+                e["mu"][col - 7 * nb] += sgn * step
             r = forward(e, Lam0=res["Lam"])
             same &= list(r["modes"]) == base_modes
             outs.append(r["vnext"])
@@ -285,13 +308,13 @@ def param_finite_differences(env: dict, res: dict | None = None, h=1e-6):
 
 
 def param_vjp(env: dict, gbar_v, res: dict | None = None):
-    """Reverse mode in the physical parameters: gbar^T dv+/d(mass, mu) split
-    into (masses, friction coefficients)."""
+    """Reverse mode in the physical parameters: gbar^T dv+/d(mass, inertia,
+    mu) split into (masses [nb], inertias [nb, 6], friction coefficients)."""
     res = res or forward(env)
     d = param_ift(env, res)
     nb = res["model"].nb
     g = np.asarray(gbar_v, dtype=np.float64) @ d["jac"]
-    return g[:nb], g[nb:]
+    return g[:nb], g[nb:7 * nb].reshape(nb, 6), g[7 * nb:]
 
 
 def finite_differences(env: dict, res: dict | None = None, h=1e-6, cols=None):

@@ -7,9 +7,9 @@ and `dsim_tangent_to_ambient` to express the q gradient in the stored
 coordinates of q.  Gradients flow to q, v and tau; the contact impulses are
 returned as a non-differentiable output.
 
-`DiffStepParams` also takes the body masses and friction coefficients as
-tensors (they replace the batch's own tables for that call) and returns
-their gradients through `dsim_step_vjp_params`.
+`DiffStepParams` also takes the body masses, rotational inertias and
+friction coefficients as tensors (they replace the batch's own tables for
+that call) and returns their gradients through `dsim_step_vjp_params`.
 """
 from __future__ import annotations
 
@@ -47,52 +47,56 @@ def diff_step(db, q, v, tau, p=None):
     return DiffStep.apply(q, v, tau, db, p or db.params())
 
 
-def _param_batch(db, mass, mu):
-    """A copy of db's batch struct whose mass and friction tables are the
-    given device tensors (kept alive by the caller)."""
+def _param_batch(db, mass, inertia, mu):
+    """A copy of db's batch struct whose mass, inertia and friction tables
+    are the given device tensors (kept alive by the caller)."""
     c = dsim.CBatch.from_buffer_copy(db.c)
     c.mass = mass.data_ptr()
+    c.inertia = inertia.data_ptr()
     if db.n_contact > 0:
         c.mu = mu.data_ptr()
     return c
 
 
 class DiffStepParams(torch.autograd.Function):
-    """v_next, lam = DiffStepParams.apply(q, v, tau, mass, mu, device_batch,
-    params): the step with the body masses [sum n_b] (positive) and friction
+    """v_next, lam = DiffStepParams.apply(q, v, tau, mass, inertia, mu,
+    device_batch, params): the step with the body masses [sum n_b]
+    (positive), rotational inertias [6 sum n_b] (xx yy zz xy xz yz about the
+    centre of mass, body frame; physically consistent) and friction
     coefficients [sum n_c] (non-negative) as differentiable inputs."""
 
     @staticmethod
-    def forward(ctx, q, v, tau, mass, mu, db, p):
+    def forward(ctx, q, v, tau, mass, inertia, mu, db, p):
         n_b = int(db.batch.body_off[-1])
         for name, t, n in (("q", q, None), ("v", v, None), ("tau", tau, None), ("mass", mass, n_b),
-                           ("mu", mu, db.n_contact)):
+                           ("inertia", inertia, 6 * n_b), ("mu", mu, db.n_contact)):
             if t.dtype != db.dtype or not t.is_contiguous() or t.device.type != db.device.type:
                 raise ValueError(f"{name} must be a contiguous {db.dtype} tensor on {db.device}")
             if n is not None and t.numel() < n:
                 raise ValueError(f"{name} needs {n} entries")
-        mass, mu = mass.detach(), mu.detach()
-        cb = _param_batch(db, mass, mu)
+        mass, inertia, mu = mass.detach(), inertia.detach(), mu.detach()
+        cb = _param_batch(db, mass, inertia, mu)
         out = dsim.step(db, q.detach(), v.detach(), tau.detach(), p, cb=cb)
-        ctx.save_for_backward(q.detach(), v.detach(), tau.detach(), mass, mu)
+        ctx.save_for_backward(q.detach(), v.detach(), tau.detach(), mass, inertia, mu)
         ctx.db, ctx.p = db, p
         ctx.mark_non_differentiable(out["lam"])
         return out["v_next"], out["lam"]
 
     @staticmethod
     def backward(ctx, g_vnext, g_lam):
-        q, v, tau, mass, mu = ctx.saved_tensors
+        q, v, tau, mass, inertia, mu = ctx.saved_tensors
         if g_vnext is None:
-            return None, None, None, None, None, None, None
-        cb = _param_batch(ctx.db, mass, mu)
+            return None, None, None, None, None, None, None, None
+        cb = _param_batch(ctx.db, mass, inertia, mu)
         o = dsim.step_vjp_params(ctx.db, g_vnext.contiguous(), q, v, tau, ctx.p, cb=cb)
         g_q = dsim.tangent_to_ambient(ctx.db, q, o["g_q"]) if ctx.needs_input_grad[0] else None
         g_mu = torch.zeros_like(mu)
         n_c = ctx.db.n_contact
         g_mu[:n_c] = o["g_mu"][:n_c]
-        return g_q, o["g_v"], o["g_tau"], o["g_mass"], g_mu, None, None
+        g_inertia = o["g_inertia"].reshape(inertia.shape)
+        return g_q, o["g_v"], o["g_tau"], o["g_mass"], g_inertia, g_mu, None, None
 
 
-def diff_step_params(db, q, v, tau, mass, mu, p=None):
+def diff_step_params(db, q, v, tau, mass, inertia, mu, p=None):
     """Differentiable step in the state and the physical parameters."""
-    return DiffStepParams.apply(q, v, tau, mass, mu, db, p or db.params())
+    return DiffStepParams.apply(q, v, tau, mass, inertia, mu, db, p or db.params())

@@ -695,63 +695,117 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
     T.sync();
 }
 
+// Generalised force of the physical parameter `col` of body-or-contact
+// layout [n_b masses, 6 n_b rotational inertias, n_c friction
+// coefficients] (the order of the parameter columns), at fixed (v+, Lam),
+// for the ID-side parameters: per body b,
+//  * mass m_b (centre of mass and rotational inertia about it fixed):
+//    F = I' A_b + V_b x* I' V_b with I' the unit point mass at the centre
+//    of mass, A_b and V_b the body's acceleration (gravity included) at a+
+//    and velocity at v;
+//  * rotational inertia component k (xx yy zz xy xz yz about the centre of
+//    mass, body frame): with the world-frame unit change dI = R E_k R^T
+//    (E_k = e_i e_i^T, or e_i e_j^T + e_j e_i^T), F = (dI alpha + omega x
+//    dI omega, 0).
+// The generalised force on dof l is S_l . F for the dofs that move b.
+DSIM_HD inline void param_force(const double* Iw, const double* Rw, const double* A, const double* V, int k,
+                                double* F) {
+    if (k < 0) {
+        const double c[3] = {Iw[1] / Iw[0], Iw[2] / Iw[0], Iw[3] / Iw[0]};
+        const double Ip[10] = {1.0, c[0], c[1], c[2], c[1] * c[1] + c[2] * c[2], c[0] * c[0] + c[2] * c[2],
+                               c[0] * c[0] + c[1] * c[1], -c[0] * c[1], -c[0] * c[2], -c[1] * c[2]};
+        double iv[6], vxiv[6];
+        iapply(Ip, A, F);
+        iapply(Ip, V, iv);
+        mxf(V, iv, vxiv);
+        for (int a = 0; a < 6; ++a) F[a] += vxiv[a];
+        return;
+    }
+    // component k: (i, j) = (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)
+    const int i = k < 3 ? k : (k == 5 ? 1 : 0);
+    const int j = k < 3 ? k : (k == 3 ? 1 : 2);
+    // body-frame angular acceleration and velocity: R^T alpha, R^T omega
+    double a[3], w[3];
+    for (int r = 0; r < 3; ++r) {
+        a[r] = Rw[r] * A[0] + Rw[3 + r] * A[1] + Rw[6 + r] * A[2];
+        w[r] = Rw[r] * V[0] + Rw[3 + r] * V[1] + Rw[6 + r] * V[2];
+    }
+    // E_k x in the body frame
+    double ea[3] = {0, 0, 0}, ew[3] = {0, 0, 0};
+    ea[i] += a[j];
+    ew[i] += w[j];
+    if (i != j) {
+        ea[j] += a[i];
+        ew[j] += w[i];
+    }
+    double wxe[3];
+    cross3(w, ew, wxe);
+    const double t[3] = {ea[0] + wxe[0], ea[1] + wxe[1], ea[2] + wxe[2]};
+    for (int r = 0; r < 3; ++r) {
+        F[r] = Rw[3 * r] * t[0] + Rw[3 * r + 1] * t[1] + Rw[3 * r + 2] * t[2];
+        F[3 + r] = 0;
+    }
+}
+
+// Slip direction of a sliding contact at the solution (sigma_T / |sigma_T|,
+// or opposite the friction impulse before any slip).
+template <class R>
+DSIM_HD inline void slip_dir(const Env<R>& E, int c, double& u0, double& u1) {
+    const double s0 = E.dsig[3 * c], s1 = E.dsig[3 * c + 1];
+    const double ns = sqrt(s0 * s0 + s1 * s1);
+    u0 = 1.0;
+    u1 = 0.0;
+    if (ns > 0) {
+        u0 = s0 / ns;
+        u1 = s1 / ns;
+    } else {
+        const double l0 = E.Ld[3 * c], l1 = E.Ld[3 * c + 1];
+        const double nl = sqrt(l0 * l0 + l1 * l1);
+        if (nl > 0) {
+            u0 = -l0 / nl;
+            u1 = -l1 / nl;
+        }
+    }
+}
+
 // Gradients of gbar . v+ in the physical parameters, after `vjp` (which
 // leaves pg = M^-1 P^T gbar, so that gbar^T dv+/dtau = dt pg^T).
 //
 // The step's residual depends on a parameter at fixed (v+, Lam) through
 // inverse dynamics or through the sliding cone, never through both, so
 // each gradient is a generalised force paired with dt pg:
-//  * mass m_b (centre of mass and rotational inertia about it fixed):
-//    dID/dm_b = S^T (I' A_b + V_b x* I' V_b) over the dofs that move b,
-//    I' the unit point mass at the centre of mass, A_b and V_b the body's
-//    acceleration (gravity included) and velocity at a+; the gradient is
-//    -(V_b(dt pg)) . (I' A_b + V_b x* I' V_b), V_b(x) the body velocity for
-//    joint velocities x.
+//  * masses and rotational inertias: the forces of `param_force`, paired
+//    with -dt pg over the dofs that move the body, i.e. -dt V_b(pg) . F
+//    with V_b(x) the body velocity for joint velocities x;
 //  * friction coefficient mu_c of a sliding contact: the tangential rows
 //    Lam_T + mu Lam_N u = 0 change like a tangential impulse -Lam_N u dmu
 //    applied outside the mode equations, i.e. a generalised force
 //    -J_c^T (Lam_N u, 0) / dt; the gradient is -Lam_N u . (J_c pg)_T.  It
 //    is zero for breaking and sticking contacts.
+// Output per environment at 7 b0 + c0: [n_b masses, 6 n_b inertias (xx yy
+// zz xy xz yz per body), n_c friction coefficients].
 template <class R>
-DSIM_HD void param_grads(const Team& T, Env<R>& E, const Params& P, R* g_mass, R* g_mu) {
-    const int n = E.nv;
+DSIM_HD void param_grads(const Team& T, Env<R>& E, const Params& P, R* gp) {
+    const int n = E.nv, nb = E.nb;
     const double* pg = E.af;
-    for (int b = T.tid; b < E.nb; b += T.nt) {
-        const double* I = E.Iw + 10 * b;
-        const double c[3] = {I[1] / I[0], I[2] / I[0], I[3] / I[0]};
-        const double Ip[10] = {1.0, c[0], c[1], c[2], c[1] * c[1] + c[2] * c[2], c[0] * c[0] + c[2] * c[2],
-                               c[0] * c[0] + c[1] * c[1], -c[0] * c[1], -c[0] * c[2], -c[1] * c[2]};
-        double f[6], iv[6], vxiv[6];
-        iapply(Ip, E.Acc + 6 * b, f);
-        iapply(Ip, E.V + 6 * b, iv);
-        mxf(E.V + 6 * b, iv, vxiv);
+    R* out = gp + 7 * size_t(E.b0) + E.c0;
+    for (int idx = T.tid; idx < 7 * nb; idx += T.nt) {
+        const int b = idx < nb ? idx : (idx - nb) / 6;
+        const int k = idx < nb ? -1 : (idx - nb) % 6;
+        double F[6];
+        param_force(E.Iw + 10 * b, E.Rw + 9 * b, E.Acc + 6 * b, E.V + 6 * b, k, F);
         double w[6] = {0, 0, 0, 0, 0, 0};
         const uint64_t mask = E.bmask[b];
         for (int j = 0; j < n; ++j)
             if ((mask >> j) & 1ull)
                 for (int a = 0; a < 6; ++a) w[a] += E.S[6 * j + a] * pg[j];
-        double s = 0;
-        for (int a = 0; a < 6; ++a) s += w[a] * (f[a] + vxiv[a]);
-        g_mass[E.b0 + b] = R(-P.dt * s);
+        out[idx] = R(-P.dt * dot6(w, F));
     }
     for (int c = T.tid; c < E.nc; c += T.nt) {
         double g = 0;
         if (E.cmode[c] == SLD) {
-            const double s0 = E.dsig[3 * c], s1 = E.dsig[3 * c + 1];
-            const double ns = sqrt(s0 * s0 + s1 * s1);
-            double u0 = 1.0, u1 = 0.0;
-            if (ns > 0) {
-                u0 = s0 / ns;
-                u1 = s1 / ns;
-            } else {
-                // no slip yet: the slip direction is opposite the friction
-                const double l0 = E.Ld[3 * c], l1 = E.Ld[3 * c + 1];
-                const double nl = sqrt(l0 * l0 + l1 * l1);
-                if (nl > 0) {
-                    u0 = -l0 / nl;
-                    u1 = -l1 / nl;
-                }
-            }
+            double u0, u1;
+            slip_dir(E, c, u0, u1);
             double j0 = 0, j1 = 0;
             for (int j = 0; j < n; ++j) {
                 j0 += double(E.J[(3 * c) * n + j]) * pg[j];
@@ -759,56 +813,38 @@ DSIM_HD void param_grads(const Team& T, Env<R>& E, const Params& P, R* g_mass, R
             }
             g = -E.Ld[3 * c + 2] * (u0 * j0 + u1 * j1);
         }
-        g_mu[E.c0 + c] = R(g);
+        out[7 * nb + c] = R(g);
     }
     T.sync();
 }
 
 // Forward-mode columns of the physical parameters, after `jacobian` (Q =
 // P M^-1 is still formed): with the generalised forces of `param_grads`,
-//   d v+ / d m_b  = -dt Q S^T (I' A_b + V_b x* I' V_b)   (dofs that move b)
-//   d v+ / d mu_c = -Q J_c^T (Lam_N u, 0)                  (sliding contacts)
-// written row-major n x (n_b + n_c) at pjac_off[e].  Each thread forms the
-// generalised force of its column on the fly (no scratch).
+//   d v+ / d (m_b or I_b,k) = -dt Q S^T F      (dofs that move b)
+//   d v+ / d mu_c           = -Q J_c^T (Lam_N u, 0)   (sliding contacts)
+// written row-major n x (7 n_b + n_c) at pjac_off[e], columns in the order
+// of `param_grads`.  Each thread forms the force of its column on the fly.
 template <class R>
 DSIM_HD void param_columns(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, R* dvdp) {
-    const int n = E.nv, nb = E.nb, nc = E.nc, np = nb + nc;
+    const int n = E.nv, nb = E.nb, nc = E.nc, np = 7 * nb + nc;
     const int off = B.pjac_off[E.e];
     for (int idx = T.tid; idx < n * np; idx += T.nt) {
         const int i = idx / np, col = idx - i * np;
         double s = 0;
-        if (col < nb) {
-            const int b = col;
-            const double* I = E.Iw + 10 * b;
-            const double c[3] = {I[1] / I[0], I[2] / I[0], I[3] / I[0]};
-            const double Ip[10] = {1.0, c[0], c[1], c[2], c[1] * c[1] + c[2] * c[2], c[0] * c[0] + c[2] * c[2],
-                                   c[0] * c[0] + c[1] * c[1], -c[0] * c[1], -c[0] * c[2], -c[1] * c[2]};
-            double f[6], iv[6], vxiv[6];
-            iapply(Ip, E.Acc + 6 * b, f);
-            iapply(Ip, E.V + 6 * b, iv);
-            mxf(E.V + 6 * b, iv, vxiv);
-            for (int a = 0; a < 6; ++a) f[a] += vxiv[a];
+        if (col < 7 * nb) {
+            const int b = col < nb ? col : (col - nb) / 6;
+            const int k = col < nb ? -1 : (col - nb) % 6;
+            double F[6];
+            param_force(E.Iw + 10 * b, E.Rw + 9 * b, E.Acc + 6 * b, E.V + 6 * b, k, F);
             const uint64_t mask = E.bmask[b];
             for (int l = 0; l < n; ++l)
-                if ((mask >> l) & 1ull) s += double(E.Q[i * n + l]) * dot6(E.S + 6 * l, f);
+                if ((mask >> l) & 1ull) s += double(E.Q[i * n + l]) * dot6(E.S + 6 * l, F);
             s *= -P.dt;
         } else {
-            const int cc = col - nb;
+            const int cc = col - 7 * nb;
             if (E.cmode[cc] == SLD) {
-                const double s0 = E.dsig[3 * cc], s1 = E.dsig[3 * cc + 1];
-                const double ns = sqrt(s0 * s0 + s1 * s1);
-                double u0 = 1.0, u1 = 0.0;
-                if (ns > 0) {
-                    u0 = s0 / ns;
-                    u1 = s1 / ns;
-                } else {
-                    const double l0 = E.Ld[3 * cc], l1 = E.Ld[3 * cc + 1];
-                    const double nl = sqrt(l0 * l0 + l1 * l1);
-                    if (nl > 0) {
-                        u0 = -l0 / nl;
-                        u1 = -l1 / nl;
-                    }
-                }
+                double u0, u1;
+                slip_dir(E, cc, u0, u1);
                 for (int l = 0; l < n; ++l)
                     s += double(E.Q[i * n + l]) *
                          (u0 * double(E.J[(3 * cc) * n + l]) + u1 * double(E.J[(3 * cc + 1) * n + l]));
@@ -850,7 +886,7 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
         if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
         if (entry == ENTRY_PVJP) {
             vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
-            param_grads(T, E, P, o4, o5);
+            param_grads(T, E, P, o4);
         }
     }
     T.sync();

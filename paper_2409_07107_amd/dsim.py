@@ -84,7 +84,7 @@ def lib():
         L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp.restype = ctypes.c_int32
-        L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13 + \
+        L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp_params.restype = ctypes.c_int32
         L.dsim_step_jacobian_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
@@ -123,9 +123,10 @@ def params(prec=F32, **overrides) -> CParams:
 
 
 def param_jac_offsets(batch) -> np.ndarray:
-    """Prefix sum of n_v (n_b + n_c): offsets of the parameter Jacobians."""
+    """Prefix sum of n_v (7 n_b + n_c): offsets of the parameter Jacobians."""
     nv = np.diff(np.asarray(batch.dof_off, dtype=np.int64))
-    npar = np.diff(np.asarray(batch.body_off, dtype=np.int64)) + np.diff(np.asarray(batch.contact_off, dtype=np.int64))
+    npar = 7 * np.diff(np.asarray(batch.body_off, dtype=np.int64)) + \
+        np.diff(np.asarray(batch.contact_off, dtype=np.int64))
     o = np.zeros(len(nv) + 1, dtype=np.int64)
     o[1:] = np.cumsum(nv * npar)
     if o[-1] >= 2 ** 31:
@@ -328,34 +329,62 @@ def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | No
     return out
 
 
+def param_index(batch):
+    """Positions in the g_params layout (per environment at 7 body_off[e] +
+    contact_off[e]: masses, inertias, friction) of the flat per-body masses
+    [sum n_b], per-body inertias [sum n_b, 6] and per-contact friction
+    coefficients [sum n_c]."""
+    bo = np.asarray(batch.body_off, dtype=np.int64)
+    co = np.asarray(batch.contact_off, dtype=np.int64)
+    nb, nc = np.diff(bo), np.diff(co)
+    base = 7 * bo[:-1] + co[:-1]
+    env_b = np.repeat(np.arange(batch.n_env), nb)
+    loc_b = np.arange(bo[-1]) - bo[:-1][env_b]
+    mass = base[env_b] + loc_b
+    inertia = (base[env_b] + nb[env_b] + 6 * loc_b)[:, None] + np.arange(6)[None, :]
+    env_c = np.repeat(np.arange(batch.n_env), nc)
+    mu = base[env_c] + 7 * nb[env_c] + (np.arange(co[-1]) - co[:-1][env_c])
+    return mass, inertia, mu
+
+
 def step_vjp_params(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None,
                     cb=None):
-    """step_vjp plus "g_mass" (per body) and "g_mu" (per contact): g^T dv+
-    with respect to the body masses and friction coefficients."""
+    """step_vjp plus "g_params" (the library's layout) and its views
+    "g_mass" [sum n_b], "g_inertia" [sum n_b, 6] (xx yy zz xy xz yz about
+    the centre of mass, body frame) and "g_mu" [sum n_c]: g^T dv+ with
+    respect to the physical parameters."""
     import torch
     p = p or db.params()
     q = db.q if q is None else q
     v = db.v if v is None else v
     tau = db.tau if tau is None else tau
+    n_par = 7 * int(db.batch.body_off[-1]) + int(db.batch.contact_off[-1])
     if out is None:
         out = _outputs(db)
         for k in ("g_q", "g_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
-        out["g_mass"] = torch.empty(int(db.batch.body_off[-1]), dtype=db.dtype, device=db.device)
-        out["g_mu"] = torch.empty(max(int(db.batch.contact_off[-1]), 1), dtype=db.dtype, device=db.device)
+        out["g_params"] = torch.empty(max(n_par, 1), dtype=db.dtype, device=db.device)
     ws, nbytes = db.workspace(p, ENTRY_VJP_PARAMS)
     _check(lib().dsim_step_vjp_params(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v),
                                       _ptr(tau), _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]),
                                       _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]),
-                                      _ptr(out["g_tau"]), _ptr(out["g_mass"]), _ptr(out["g_mu"]), _ptr(ws),
+                                      _ptr(out["g_tau"]), _ptr(out["g_params"]), _ptr(ws),
                                       ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    if not hasattr(db, "_param_index"):
+        db._param_index = tuple(torch.as_tensor(a, dtype=torch.int64, device=db.device)
+                                for a in param_index(db.batch))
+    im, ii, imu = db._param_index
+    gp = out["g_params"]
+    out["g_mass"] = gp[im]
+    out["g_inertia"] = gp[ii]
+    out["g_mu"] = gp[imu] if imu.numel() else torch.zeros(1, dtype=db.dtype, device=db.device)
     return out
 
 
 def step_jacobian_params(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
-    """step_jacobian plus "dvdp": per environment the n_v x (n_b + n_c)
-    derivative of v+ in the body masses and friction coefficients, at
-    param_jac_offsets(batch)."""
+    """step_jacobian plus "dvdp": per environment the n_v x (7 n_b + n_c)
+    derivative of v+ in the body masses, rotational inertias and friction
+    coefficients (the g_params order), at param_jac_offsets(batch)."""
     import torch
     p = p or db.params()
     q = db.q if q is None else q

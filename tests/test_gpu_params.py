@@ -2,7 +2,7 @@
 columns dv+/d(body masses, friction coefficients) of
 dsim_step_jacobian_params and the reverse mode gbar^T dv+/d(...) of
 dsim_step_vjp_params, against the oracle's implicit differentiation of the
-mode system, on
+mode system (body masses, rotational inertias, friction coefficients), on
 seeded batches (a sliding cube without spin, arms, pressed bodies in gap
 mode 1 with Baumgarte gains, and sampled environments of the full-size
 tree36 and ragged batches launched whole)."""
@@ -28,6 +28,20 @@ def _load(name):
 
 # the largest ragged trees exceed a compute unit's LDS in the FP64 form (the
 # whole call is rejected with DSIM_ERR_SIZE), so the ragged set runs in FP32
+# The rotational-inertia entries are compared on their own, relative to the
+# whole block's norm.  They pair the change of inertia with the body's
+# angular acceleration (omega+ - omega)/dt.  That acceleration vanishes for
+# a body the contacts keep from turning (a sliding cube), yet omega+ only
+# satisfies the contact constraints of the J the form rounds.  So
+# the entries carry about eps |v| / dt of noise, amplified through Q:
+# measured up to 2e-3 of the block in the FP32 form and 1.3e-10 in FP64.
+TOL_INERTIA = {0: 1e-9, 1: 1e-2}
+
+
+def _split(block, nb):
+    """(masses and friction, inertias) of a parameter block or vector."""
+    idx = np.r_[0:nb, 7 * nb:block.shape[-1]]
+    return block[..., idx], block[..., nb:7 * nb]
 CASES = [(n, p) for n in sorted(PARAMS) for p in (0, 1) if not (n.startswith("params_mixed") and p == 0)]
 
 
@@ -42,12 +56,11 @@ def test_param_vjp_matches_oracle(name, precision, gpu_lib):
     say(f"param vjp {name} precision {precision} n_env {batch.n_env}")
     out = dsim.step_vjp_params(db, torch.as_tensor(gbar, dtype=db.dtype, device=db.device))
     torch.cuda.synchronize()
-    gm = out["g_mass"].double().cpu().numpy()
-    gmu = out["g_mu"].double().cpu().numpy()
+    gp = out["g_params"].double().cpu().numpy()
     modes = out["mode"].cpu().numpy()
     status = out["status"].cpu().numpy()
     tol = TOL[precision]
-    worst, n = 0.0, 0
+    worst, worst_i, n = 0.0, 0.0, 0
     for i, e in enumerate(envs):
         b0, b1 = batch.body_off[e], batch.body_off[e + 1]
         c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
@@ -56,14 +69,19 @@ def test_param_vjp_matches_oracle(name, precision, gpu_lib):
                 not np.array_equal(modes[c0:c1].astype(np.int8), gold["modes"][i].astype(np.int8)):
             continue
         ref = gbar[d0:d1] @ gold["pjac"][i]
-        got = np.concatenate([gm[b0:b1], gmu[c0:c1]])
-        worst = max(worst, np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-8))
+        base = 7 * b0 + c0
+        got = gp[base:base + ref.size]
+        scale = max(np.linalg.norm(ref), 1e-8)
+        (gm, gi), (rm, ri) = _split(got, b1 - b0), _split(ref, b1 - b0)
+        worst = max(worst, np.linalg.norm(gm - rm) / scale)
+        worst_i = max(worst_i, np.linalg.norm(gi - ri) / scale)
         n += 1
-    say(f"  compared {n} of {len(envs)} envs, worst relative error {worst:.2e}")
+    say(f"  compared {n} of {len(envs)} envs, worst relative error {worst:.2e} (inertias {worst_i:.2e})")
     # ragged trees often have several NCP solutions or small mode margins
     # (validated and reported by the Jacobian parity tests, not gated here)
     assert n >= len(envs) // (4 if name.startswith("params_mixed") else 2)
     assert worst <= tol["jac"]
+    assert worst_i <= TOL_INERTIA[precision]
 
 
 @pytest.mark.parametrize("workload,precision", [("mixed", 1), ("tree36", 0), ("tree36", 1)])
@@ -85,7 +103,12 @@ def test_param_entry_shares_the_vjp(workload, precision, gpu_lib):
     mode = b["mode"][:n_c].cpu().numpy()
     gmu = b["g_mu"][:n_c].cpu().numpy()
     assert np.all(gmu[mode != dsim.MODE_SLIDE] == 0)
-    assert np.isfinite(b["g_mass"].cpu().numpy()).all()
+    assert np.isfinite(b["g_params"].cpu().numpy()).all()
+    # the flat views index the library's layout
+    im, ii, imu = dsim.param_index(batch)
+    gp = b["g_params"].cpu().numpy()
+    assert np.array_equal(b["g_mass"].cpu().numpy(), gp[im])
+    assert np.array_equal(b["g_inertia"].cpu().numpy(), gp[ii])
 
 
 @pytest.mark.parametrize("name,precision", CASES)
@@ -103,7 +126,7 @@ def test_param_columns_match_oracle(name, precision, gpu_lib):
     modes = out["mode"].cpu().numpy()
     status = out["status"].cpu().numpy()
     tol = TOL[precision]
-    worst, n = 0.0, 0
+    worst, worst_i, n = 0.0, 0.0, 0
     for i, e in enumerate(envs):
         c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
         if not (gold["ok"][i] and gold["unique"][i] and gold["margin"][i] >= tol["margin"]) or status[e] & 17 or \
@@ -111,11 +134,16 @@ def test_param_columns_match_oracle(name, precision, gpu_lib):
             continue
         ref = gold["pjac"][i]
         got = dvdp[po[e]:po[e + 1]].reshape(ref.shape)
-        worst = max(worst, np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-8))
+        nb = batch.body_off[e + 1] - batch.body_off[e]
+        scale = max(np.linalg.norm(ref), 1e-8)
+        (gm, gi), (rm, ri) = _split(got, nb), _split(ref, nb)
+        worst = max(worst, np.linalg.norm(gm - rm) / scale)
+        worst_i = max(worst_i, np.linalg.norm(gi - ri) / scale)
         n += 1
-    say(f"  compared {n} of {len(envs)} envs, worst relative error {worst:.2e}")
+    say(f"  compared {n} of {len(envs)} envs, worst relative error {worst:.2e} (inertias {worst_i:.2e})")
     assert n >= len(envs) // (4 if name.startswith("params_mixed") else 2)
     assert worst <= tol["jac"]
+    assert worst_i <= TOL_INERTIA[precision]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -137,7 +165,7 @@ def test_param_columns_agree_with_the_reverse_mode(precision, gpu_lib):
     po = dsim.param_jac_offsets(batch)
     dvdp = fj["dvdp"].double().cpu().numpy()
     g = gbar.double().cpu().numpy()
-    gm, gmu = rv["g_mass"].double().cpu().numpy(), rv["g_mu"].double().cpu().numpy()
+    gp = rv["g_params"].double().cpu().numpy()
     status = fj["status"].cpu().numpy()
     tol = 1e-11 if precision == 0 else 1e-4
     for e in range(batch.n_env):
@@ -146,9 +174,10 @@ def test_param_columns_agree_with_the_reverse_mode(precision, gpu_lib):
         d0, d1 = batch.dof_off[e], batch.dof_off[e + 1]
         b0, b1 = batch.body_off[e], batch.body_off[e + 1]
         c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
-        blk = dvdp[po[e]:po[e + 1]].reshape(d1 - d0, (b1 - b0) + (c1 - c0))
+        blk = dvdp[po[e]:po[e + 1]].reshape(d1 - d0, 7 * (b1 - b0) + (c1 - c0))
         ref = g[d0:d1] @ blk
-        got = np.concatenate([gm[b0:b1], gmu[c0:c1]])
+        base = 7 * b0 + c0
+        got = gp[base:base + ref.size]
         assert np.linalg.norm(got - ref) <= tol * max(np.linalg.norm(ref), 1e-8), e
 
 
@@ -163,23 +192,27 @@ def test_autograd_in_the_physical_parameters(gpu_lib):
     batch = scenes.make("arm7", 16, seed=8)
     db = dsim.DeviceBatch(batch, precision=0)
     mass = db.arrays["mass"].clone().requires_grad_(True)
+    inertia = db.arrays["inertia"].clone().requires_grad_(True)
     mu = db.arrays["mu"].clone().requires_grad_(True)
     w = torch.as_tensor(np.random.default_rng(4).normal(size=db.n_dof), dtype=db.dtype, device=db.device)
-    vn, _ = diff_step_params(db, db.q, db.v, db.tau, mass, mu)
+    vn, _ = diff_step_params(db, db.q, db.v, db.tau, mass, inertia, mu)
     (vn * w).sum().backward()
     ref = dsim.step_vjp_params(db, w)
     torch.cuda.synchronize()
     assert torch.equal(vn, ref["v_next"])
     assert torch.equal(mass.grad, ref["g_mass"])
+    assert torch.equal(inertia.grad.reshape(-1, 6), ref["g_inertia"])
     assert torch.equal(mu.grad[:db.n_contact], ref["g_mu"][:db.n_contact])
     # a heavier first link and a different friction table
     b2 = copy.deepcopy(batch)
     b2.mass = np.array(batch.mass, dtype=np.float64)
     b2.mu = np.array(batch.mu, dtype=np.float64)
+    b2.inertia = np.array(batch.inertia, dtype=np.float64)
     b2.mass[batch.body_off[3]] *= 1.5
+    b2.inertia[batch.body_off[2]] *= 1.3
     b2.mu[:] = np.linspace(0.2, 1.0, len(b2.mu))
     db2 = dsim.DeviceBatch(b2, precision=0)
-    vn2, _ = diff_step_params(db, db.q, db.v, db.tau, db2.arrays["mass"], db2.arrays["mu"])
+    vn2, _ = diff_step_params(db, db.q, db.v, db.tau, db2.arrays["mass"], db2.arrays["inertia"], db2.arrays["mu"])
     ref2 = dsim.step(db2)
     torch.cuda.synchronize()
     assert torch.equal(vn2, ref2["v_next"])

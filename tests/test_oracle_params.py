@@ -1,4 +1,5 @@
-"""Pins of the oracle's physical-parameter derivatives dv+/d(mass, mu)
+"""Pins of the oracle's physical-parameter derivatives dv+/d(mass, inertia,
+mu)
 (the parameter columns of the implicit differentiation of Section II.D and
 III): closed forms of the sliding point mass in every mode, and central
 differences of the whole step on small systems (gap modes 0 and 1)."""
@@ -25,8 +26,10 @@ def test_point_mass_parameter_derivatives(case):
     assert r["modes"] == [{"brk": ncp.BRK, "stk": ncp.STK, "sld": ncp.SLD}[case]]
     d = derivative.param_ift(env, r)
     assert d["unique_v"]
-    dm, dmu = d["jac"][:3, 0], d["jac"][:3, 1]
+    dm, dmu = d["jac"][:3, 0], d["jac"][:3, 7]
     assert np.abs(d["jac"][3:]).max() < 1e-13  # the contact is at the COM: no turning
+    # no spin, no angular acceleration: the rotational inertia does not act
+    assert np.abs(d["jac"][:, 1:7]).max() < 1e-13
     vf = np.array(v) + DT * (tau / m + np.array([0, 0, GZ]))
     dvf = -DT * tau / m ** 2  # d v_f / d m
     if case == "brk":
@@ -88,7 +91,7 @@ def test_mu_columns_vanish_off_the_sliding_contacts():
     nb = len(env["mass"])
     for c, md in enumerate(r["modes"]):
         if md != ncp.SLD:
-            assert np.abs(d["jac"][:, nb + c]).max() < 1e-12
+            assert np.abs(d["jac"][:, 7 * nb + c]).max() < 1e-12
 
 
 def test_param_vjp_is_gbar_times_the_columns():
@@ -96,8 +99,31 @@ def test_param_vjp_is_gbar_times_the_columns():
     env = b.env(0)
     r = forward(env)
     g = np.random.default_rng(0).normal(size=len(env["v"]))
-    gm, gmu = derivative.param_vjp(env, g, r)
+    gm, gi, gmu = derivative.param_vjp(env, g, r)
     d = derivative.param_ift(env, r)
     nb = len(env["mass"])
     assert np.allclose(gm, g @ d["jac"][:, :nb], atol=1e-14)
-    assert np.allclose(gmu, g @ d["jac"][:, nb:], atol=1e-14)
+    assert np.allclose(gi.reshape(-1), g @ d["jac"][:, nb:7 * nb], atol=1e-14)
+    assert np.allclose(gmu, g @ d["jac"][:, 7 * nb:], atol=1e-14)
+
+
+def test_spinning_free_body_inertia_closed_form():
+    """A free body with no contact, spinning about a body axis with a
+    torque: the angular velocity obeys I w' + w x I w = tau (body frame), so
+    d w+ / d I_xx = -dt I^-1 (e_x e_x^T w' + w x e_x e_x^T w)."""
+    from paper_2409_07107_amd import scenes as sc
+    I = np.array([0.02, 0.03, 0.05])
+    b = sc.body(-1, sc.FREEFLYER, mass=1.2, inertia=(I[0], I[1], I[2], 0, 0, 0))
+    w = np.array([0.4, -0.7, 1.1])
+    tq = np.array([0.01, 0.02, -0.015])
+    rec = sc.record([b], [], [0, 0, 1.0, 0, 0, 0, 1.0], np.r_[0, 0, 0, w], np.r_[0, 0, 0, tq])
+    env = sc.assemble([rec]).env(0)
+    r = forward(env)
+    d = derivative.param_ift(env, r)
+    Iw = I * w
+    wdot = (tq - np.cross(w, Iw)) / I
+    for k in range(3):
+        E = np.zeros((3, 3))
+        E[k, k] = 1.0
+        ref = -DT * (E @ wdot + np.cross(w, E @ w)) / I
+        assert np.abs(d["jac"][3:, 1 + k] - ref).max() < 1e-5 * np.abs(ref).max() + 1e-15
