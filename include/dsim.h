@@ -229,13 +229,17 @@ int32_t dsim_step_jacobian(const dsim_batch* batch, const dsim_params* params,
 
 /*
  * Reverse mode (Section III.A, the adjoint of the implicit system): recomputes
- * the step and returns g_q = gbar^T dv+/ddq, g_v = gbar^T dv+/dv and
- * g_tau = gbar^T dv+/dtau for gbar = g_vnext [sum n_v].  Also writes the step
- * outputs (v_next, lam, mode, status).
+ * the step and returns g_q, g_v, g_tau, the gradients with respect to
+ * (dq, v, tau) of gbar . v+ + glam . Lam for gbar = g_vnext [sum n_v] and
+ * glam = g_lam [3 sum n_c] (may be NULL: no impulse term).  Also writes the
+ * step outputs (v_next, lam, mode, status).  The impulse term uses the
+ * derivative of the impulses the library computes; with redundant contacts
+ * (a rank-deficient reduced system) the impulses, and so this term, are
+ * one of several valid choices, while the v+ term is unique.
  */
 int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
                       const void* q, const void* v, const void* tau,
-                      const void* g_vnext,
+                      const void* g_vnext, const void* g_lam,
                       void* v_next, void* lam, int8_t* mode, int32_t* status,
                       void* g_q, void* g_v, void* g_tau,
                       void* ws, size_t ws_bytes, void* stream);
@@ -243,7 +247,8 @@ int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
 /*
  * Reverse mode in the physical parameters as well (derivatives with respect
  * to physical parameters, Section II.D, by the implicit differentiation of
- * the same mode system): everything dsim_step_vjp computes, plus g_params
+ * the same mode system): everything dsim_step_vjp computes (g_lam as
+ * there), plus g_params
  * [7 sum n_b + sum n_c], per environment e at 7 body_off[e] + contact_off[e]:
  *   n_b entries gbar^T dv+/dm_b (body masses; the centre of mass and the
  *     rotational inertia about it held fixed),
@@ -258,7 +263,7 @@ int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
  */
 int32_t dsim_step_vjp_params(const dsim_batch* batch, const dsim_params* params,
                              const void* q, const void* v, const void* tau,
-                             const void* g_vnext,
+                             const void* g_vnext, const void* g_lam,
                              void* v_next, void* lam, int8_t* mode, int32_t* status,
                              void* g_q, void* g_v, void* g_tau, void* g_params,
                              void* ws, size_t ws_bytes, void* stream);

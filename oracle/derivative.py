@@ -349,9 +349,13 @@ def finite_differences(env: dict, res: dict | None = None, h=1e-6, cols=None):
     return jac, valid
 
 
-def vjp(env: dict, gbar_v, res: dict | None = None):
-    """Reverse mode: gbar^T dv+/dtheta split into (dq, v, tau) parts."""
+def vjp(env: dict, gbar_v, res: dict | None = None, gbar_lam=None):
+    """Reverse mode: gbar^T dv+/dtheta (+ gbar_lam^T dLam/dtheta) split into
+    (dq, v, tau) parts.  The impulse term is unique only when dF/dy has
+    full rank (ift's rank == size)."""
     d = ift(env, res)
     nv = d["jac"].shape[0]
     g = np.asarray(gbar_v, dtype=np.float64) @ d["jac"]
+    if gbar_lam is not None and d["dLam"].size:
+        g = g + np.asarray(gbar_lam, dtype=np.float64) @ d["dLam"]
     return g[:nv], g[nv:2 * nv], g[2 * nv:]

@@ -4,8 +4,8 @@ forward runs `dsim_step`; backward runs `dsim_step_vjp`, the library's
 reverse mode through the implicit contact system (Section III.A), which
 recomputes the step from the saved inputs instead of storing its internals,
 and `dsim_tangent_to_ambient` to express the q gradient in the stored
-coordinates of q.  Gradients flow to q, v and tau; the contact impulses are
-returned as a non-differentiable output.
+coordinates of q.  Gradients flow to q, v and tau from both outputs, v+
+and the contact impulses.
 
 `DiffStepParams` also takes the body masses, rotational inertias and
 friction coefficients as tensors (they replace the batch's own tables for
@@ -19,7 +19,9 @@ from . import dsim
 
 
 class DiffStep(torch.autograd.Function):
-    """v_next, lam = DiffStep.apply(q, v, tau, device_batch, params)."""
+    """v_next, lam = DiffStep.apply(q, v, tau, device_batch, params).  Both
+    outputs are differentiable; the impulse gradient uses the library's
+    impulse derivative, one valid choice when contacts are redundant."""
 
     @staticmethod
     def forward(ctx, q, v, tau, db, p):
@@ -29,15 +31,19 @@ class DiffStep(torch.autograd.Function):
         out = dsim.step(db, q.detach(), v.detach(), tau.detach(), p)
         ctx.save_for_backward(q.detach(), v.detach(), tau.detach())
         ctx.db, ctx.p = db, p
-        ctx.mark_non_differentiable(out["lam"])
         return out["v_next"], out["lam"]
 
     @staticmethod
     def backward(ctx, g_vnext, g_lam):
         q, v, tau = ctx.saved_tensors
-        if g_vnext is None:
+        if g_vnext is None and g_lam is None:
             return None, None, None, None, None
-        o = dsim.step_vjp(ctx.db, g_vnext.contiguous(), q, v, tau, ctx.p)
+        if g_vnext is None:
+            g_vnext = torch.zeros_like(v)
+        gl = None
+        if g_lam is not None and ctx.db.n_contact > 0:
+            gl = g_lam.contiguous()
+        o = dsim.step_vjp(ctx.db, g_vnext.contiguous(), q, v, tau, ctx.p, g_lam=gl)
         g_q = dsim.tangent_to_ambient(ctx.db, q, o["g_q"]) if ctx.needs_input_grad[0] else None
         return g_q, o["g_v"], o["g_tau"], None, None
 

@@ -416,19 +416,19 @@ int32_t dsim_step_jacobian_params(const dsim_batch* b, const dsim_params* p, con
 }
 
 int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
-                      const void* g_vnext, void* v_next, void* lam, int8_t* mode, int32_t* status, void* g_q,
-                      void* g_v, void* g_tau, void* ws, size_t ws_bytes, void* stream) {
+                      const void* g_vnext, const void* g_lam, void* v_next, void* lam, int8_t* mode,
+                      int32_t* status, void* g_q, void* g_v, void* g_tau, void* ws, size_t ws_bytes, void* stream) {
     if (!g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
-    return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, nullptr, v_next, lam, mode, status, g_q, g_v, g_tau,
+    return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, g_lam, v_next, lam, mode, status, g_q, g_v, g_tau,
                                nullptr, nullptr, ws, ws_bytes, stream);
 }
 
 int32_t dsim_step_vjp_params(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
-                             const void* tau, const void* g_vnext, void* v_next, void* lam, int8_t* mode,
-                             int32_t* status, void* g_q, void* g_v, void* g_tau, void* g_params, void* ws,
-                             size_t ws_bytes, void* stream) {
+                             const void* tau, const void* g_vnext, const void* g_lam, void* v_next, void* lam,
+                             int8_t* mode, int32_t* status, void* g_q, void* g_v, void* g_tau, void* g_params,
+                             void* ws, size_t ws_bytes, void* stream) {
     if (!g_vnext || !g_q || !g_v || !g_tau || !g_params) return DSIM_ERR_ARG;
-    return dispatch<ENTRY_PVJP>(b, p, q, v, tau, g_vnext, nullptr, v_next, lam, mode, status, g_q, g_v, g_tau,
+    return dispatch<ENTRY_PVJP>(b, p, q, v, tau, g_vnext, g_lam, v_next, lam, mode, status, g_q, g_v, g_tau,
                                 g_params, nullptr, ws, ws_bytes, stream);
 }
 

@@ -624,7 +624,7 @@ DSIM_HD void integrate_adjoint(const Team& T, Env<R>& E, const Params& P, const 
 // q part added to gq.
 template <class R>
 DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* gbar, const R* aqn,
-                 R* gq, R* gv, R* gtau) {
+                 const R* glam, R* gq, R* gv, R* gtau) {
     const int n = E.nv, k = E.k, m = E.hdr[1], rank = E.hdr[4];
     derivative_partials(T, E, P);
     double* gb = E.bias;  // gbar (the bias is no longer needed)
@@ -644,6 +644,8 @@ DSIM_HD void vjp(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& 
             for (int a = 0; a < 3; ++a) {
                 double ka = 0;
                 for (int j = 0; j < n; ++j) ka += double(E.KT[(3 * c + a) * n + j]) * gb[j];
+                // an adjoint of the impulses enters beside K^T gbar: dLam = C X
+                if (glam) ka += double(glam[3 * E.c0 + 3 * c + a]);
                 s += E.vcol[3 * i + a] * ka;
             }
             sp[i] = s;
@@ -882,10 +884,12 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
             jacobian(T, E, B, P, o1, o2, o3);
             param_columns(T, E, B, P, o4);
         }
-        if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
-        if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, o1, o2, o3);
+        // the VJP entries take the impulse adjoint in gbar2; the rollout
+        // adjoint takes the position adjoint there
+        if (entry == ENTRY_VJP) vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), gbar2, o1, o2, o3);
+        if (entry == ENTRY_RVJP) vjp(T, E, B, P, gbar, gbar2, static_cast<const R*>(nullptr), o1, o2, o3);
         if (entry == ENTRY_PVJP) {
-            vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), o1, o2, o3);
+            vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), gbar2, o1, o2, o3);
             param_grads(T, E, P, o4);
         }
     }

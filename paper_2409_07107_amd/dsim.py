@@ -81,10 +81,10 @@ def lib():
         L.dsim_step_jacobian.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 10 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_jacobian.restype = ctypes.c_int32
-        L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
+        L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp.restype = ctypes.c_int32
-        L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
+        L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp_params.restype = ctypes.c_int32
         L.dsim_step_jacobian_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 11 + \
@@ -310,8 +310,10 @@ def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None =
     return out
 
 
-def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
-    """The step plus g^T dv+/d(dq, v, tau) for g = g_vnext (per environment)."""
+def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None,
+             g_lam=None):
+    """The step plus the gradients in (dq, v, tau) of g_vnext . v+ (+ g_lam .
+    Lam when g_lam [3 sum n_c] is given)."""
     import torch
     p = p or db.params()
     q = db.q if q is None else q
@@ -323,7 +325,7 @@ def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | No
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
     ws, nbytes = db.workspace(p, ENTRY_VJP)
     _check(lib().dsim_step_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
-                               _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
+                               _ptr(g_vnext), _ptr(g_lam), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]), _ptr(out["g_tau"]),
                                _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
     return out
@@ -348,7 +350,7 @@ def param_index(batch):
 
 
 def step_vjp_params(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None,
-                    cb=None):
+                    cb=None, g_lam=None):
     """step_vjp plus "g_params" (the library's layout) and its views
     "g_mass" [sum n_b], "g_inertia" [sum n_b, 6] (xx yy zz xy xz yz about
     the centre of mass, body frame) and "g_mu" [sum n_c]: g^T dv+ with
@@ -366,7 +368,7 @@ def step_vjp_params(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CPara
         out["g_params"] = torch.empty(max(n_par, 1), dtype=db.dtype, device=db.device)
     ws, nbytes = db.workspace(p, ENTRY_VJP_PARAMS)
     _check(lib().dsim_step_vjp_params(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v),
-                                      _ptr(tau), _ptr(g_vnext), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                      _ptr(tau), _ptr(g_vnext), _ptr(g_lam), _ptr(out["v_next"]), _ptr(out["lam"]),
                                       _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]),
                                       _ptr(out["g_tau"]), _ptr(out["g_params"]), _ptr(ws),
                                       ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))

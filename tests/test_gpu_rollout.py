@@ -239,3 +239,52 @@ def test_long_rollout_directional_derivative(gpu_lib):
             say(f"env {e}: fd {fd[e]:.6e} analytic {an:.6e}")
     say(f"directional derivative agrees on {agree} of {clean} unflagged environments ({batch.n_env} in all)")
     assert agree >= 4 and agree >= 0.7 * clean
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vjp_with_impulse_adjoint(precision, gpu_lib):
+    """g_v . v+ + g_lam . Lam: against the oracle where its impulse
+    derivative is unique (full-rank implicit system), and through DiffStep
+    with both outputs in the loss."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    from paper_2409_07107_amd.autograd import diff_step
+    from oracle import derivative
+    from oracle.step import forward
+    from tests.gap_scenes import pressed_bodies
+    batch = scenes.concat([pressed_bodies(6, seed=21, kp=0.0, kd=0.0), ])
+    batch2 = scenes.make("arm7", 16, seed=23)
+    for b in (batch, batch2):
+        db = _db(b, precision)
+        rng = np.random.default_rng(8)
+        gv = rng.normal(size=db.n_dof)
+        gl = rng.normal(size=3 * db.n_contact)
+        tv = torch.as_tensor(gv, dtype=db.dtype, device=db.device)
+        tl = torch.as_tensor(gl, dtype=db.dtype, device=db.device)
+        o = dsim.step_vjp(db, tv, g_lam=tl)
+        torch.cuda.synchronize()
+        status = o["status"].cpu().numpy()
+        tol = TOL[precision]["jac"]
+        n = 0
+        for e in range(b.n_env):
+            env = b.env(e)
+            r = forward(env)
+            d = derivative.ift(env, r)
+            if status[e] & 17 or d["rank"] != d["size"] or not r["info"]["ok"] or r["margin"] < TOL[precision]["margin"]:
+                continue
+            d0, d1 = b.dof_off[e], b.dof_off[e + 1]
+            c0, c1 = b.contact_off[e], b.contact_off[e + 1]
+            ref = np.concatenate(derivative.vjp(env, gv[d0:d1], r, gbar_lam=gl[3 * c0:3 * c1]))
+            got = np.concatenate([o[k][d0:d1].double().cpu().numpy() for k in ("g_q", "g_v", "g_tau")])
+            assert np.linalg.norm(got - ref) <= tol * max(np.linalg.norm(ref), 1e-8), (e, np.linalg.norm(got - ref))
+            n += 1
+        say(f"impulse adjoint: {n} of {b.n_env} envs with a unique impulse derivative compared")
+        assert n >= 2
+        # autograd with both outputs in the loss
+        q = db.q.clone().requires_grad_(True)
+        v = db.v.clone().requires_grad_(True)
+        tau = db.tau.clone().requires_grad_(True)
+        vn, lam = diff_step(db, q, v, tau)
+        ((vn * tv).sum() + (lam[:3 * db.n_contact] * tl).sum()).backward()
+        torch.cuda.synchronize()
+        assert torch.equal(v.grad, o["g_v"]) and torch.equal(tau.grad, o["g_tau"])

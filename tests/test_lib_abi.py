@@ -117,7 +117,7 @@ def test_null_arguments_are_rejected(L):
     assert L.dsim_step(ctypes.byref(cb), None, *([None] * 7), None, 0, None) == -1
     assert L.dsim_step(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), None, 0, None) == -1
     assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([None] * 10), None, 0, None) == -1
-    assert L.dsim_step_vjp_params(ctypes.byref(cb), ctypes.byref(p), *([None] * 12), None, 0, None) == -1
+    assert L.dsim_step_vjp_params(ctypes.byref(cb), ctypes.byref(p), *([None] * 13), None, 0, None) == -1
     assert L.dsim_step_jacobian_params(ctypes.byref(cb), ctypes.byref(p), *([None] * 11), None, 0, None) == -1
 
 
