@@ -325,6 +325,22 @@ int32_t dsim_step_integrate_vjp(const dsim_batch* batch, const dsim_params* para
 int32_t dsim_tangent_to_ambient(const dsim_batch* batch, int32_t precision, const void* q,
                                 const void* g_tangent, void* g_ambient, void* stream);
 
+/*
+ * The transpose of that map: a gradient on the stored coordinates of q
+ * (g_ambient [sum n_q]) -> the tangent adjoint g_tangent [sum n_v] =
+ * (d (q (+) delta) / d delta)^T g_ambient at delta = 0, the form the VJP
+ * entries take for q_next (for instance a loss gradient on the stored
+ * coordinates of q_next from torch autograd).  Revolute entries copy; a
+ * free flyer gets R(quat)^T g_p and (w g_v - v x g_v - v g_w) / 2 for a
+ * quaternion (v, w) with gradient (g_v, g_w).  The two maps compose to the
+ * identity on tangent gradients for unit quaternions.
+ */
+int32_t dsim_ambient_to_tangent(const dsim_batch* batch, int32_t precision, const void* q,
+                                const void* g_ambient, void* g_tangent, void* stream);
+
+/* Description of one status bit (DSIM_ST_*), or "ok" for 0. */
+const char* dsim_status_string(int32_t bit);
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,3 +106,38 @@ class DiffStepParams(torch.autograd.Function):
 def diff_step_params(db, q, v, tau, mass, inertia, mu, p=None):
     """Differentiable step in the state and the physical parameters."""
     return DiffStepParams.apply(q, v, tau, mass, inertia, mu, db, p or db.params())
+
+
+class DiffStepIntegrate(torch.autograd.Function):
+    """q_next, v_next = DiffStepIntegrate.apply(q, v, tau, device_batch,
+    params): the step followed by q_next = q (+) dt v_next, one fused launch
+    forward and one `dsim_step_integrate_vjp` backward (the q_next gradient,
+    on its stored coordinates, is first taken to the tangent by
+    `dsim_ambient_to_tangent`).  Composes into rollouts, for instance under
+    torch.utils.checkpoint."""
+
+    @staticmethod
+    def forward(ctx, q, v, tau, db, p):
+        for name, t in (("q", q), ("v", v), ("tau", tau)):
+            if t.dtype != db.dtype or not t.is_contiguous() or t.device.type != db.device.type:
+                raise ValueError(f"{name} must be a contiguous {db.dtype} tensor on {db.device}")
+        out = dsim.step_integrate(db, q.detach(), v.detach(), tau.detach(), p)
+        ctx.save_for_backward(q.detach(), v.detach(), tau.detach(), out["q_next"])
+        ctx.db, ctx.p = db, p
+        return out["q_next"], out["v_next"]
+
+    @staticmethod
+    def backward(ctx, g_qnext, g_vnext):
+        q, v, tau, qn = ctx.saved_tensors
+        db = ctx.db
+        a_q = dsim.ambient_to_tangent(db, qn, g_qnext.contiguous()) if g_qnext is not None else \
+            torch.zeros(db.n_dof, dtype=db.dtype, device=db.device)
+        a_v = g_vnext.contiguous() if g_vnext is not None else torch.zeros_like(v)
+        o = dsim.step_integrate_vjp(db, a_q, a_v, q, v, tau, ctx.p)
+        g_q = dsim.tangent_to_ambient(db, q, o["a_q"]) if ctx.needs_input_grad[0] else None
+        return g_q, o["a_v"], o["g_tau"], None, None
+
+
+def diff_step_integrate(db, q, v, tau, p=None):
+    """Differentiable fused step and position update: returns (q_next, v_next)."""
+    return DiffStepIntegrate.apply(q, v, tau, db, p or db.params())

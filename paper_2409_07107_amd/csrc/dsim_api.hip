@@ -162,6 +162,44 @@ __global__ __launch_bounds__(64) void ambient_kernel(BatchView<R> B, const R* q,
     }
 }
 
+// The transpose of the tangent map: a gradient on the stored coordinates of q
+// -> the tangent adjoint, g_tangent = (d (q (+) delta) / d delta)^T g_ambient
+// at delta = 0.  Revolute entries copy; a free flyer gets R(quat)^T g_p for
+// the linear part and (w g_v - v x g_v - v g_w) / 2 for the angular part,
+// with (v, w) the quaternion's vector and scalar parts and (g_v, g_w) the
+// gradient on them (the differential of quat * exp(delta / 2)).
+template <class R>
+__global__ __launch_bounds__(64) void tangent_kernel(BatchView<R> B, const R* q, const R* ga, R* gt) {
+    const int e = blockIdx.x;
+    const int b0 = B.body_off[e], nb = B.body_off[e + 1] - b0;
+    const int q0 = B.cfg_off[e], d0 = B.dof_off[e];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        int cfg = 0, dof = 0;
+        for (int i = 0; i < b; ++i) {
+            const bool ff = B.jtype[b0 + i] == 1;
+            cfg += ff ? 7 : 1;
+            dof += ff ? 6 : 1;
+        }
+        const R* qq = q + q0 + cfg;
+        const R* g = ga + q0 + cfg;
+        R* o = gt + d0 + dof;
+        if (B.jtype[b0 + b] == 1) {
+            const double x = qq[3], y = qq[4], z = qq[5], w = qq[6];
+            const double Rm[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                                  2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                                  2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)};
+            for (int i = 0; i < 3; ++i)
+                o[i] = R(Rm[i] * double(g[0]) + Rm[3 + i] * double(g[1]) + Rm[6 + i] * double(g[2]));
+            const double gx = g[3], gy = g[4], gz = g[5], gw = g[6];
+            o[3] = R(0.5 * (w * gx - (y * gz - z * gy) - x * gw));
+            o[4] = R(0.5 * (w * gy - (z * gx - x * gz) - y * gw));
+            o[5] = R(0.5 * (w * gz - (x * gy - y * gx) - z * gw));
+        } else {
+            o[0] = g[0];
+        }
+    }
+}
+
 int check_common(const dsim_batch* b, const dsim_params* p) {
     if (!b || !p) return DSIM_ERR_ARG;
     int rc = dsim_validate_params(p);
@@ -288,6 +326,19 @@ const char* dsim_error_string(int32_t code) {
         case DSIM_ERR_MODEL: return "non-physical model";
         case DSIM_ERR_DEVICE: return "no usable gfx950 device";
         default: return "unknown error";
+    }
+}
+
+const char* dsim_status_string(int32_t bit) {
+    switch (bit) {
+        case DSIM_ST_NCP_NOT_CONVERGED: return "NCP residual above ncp_tol";
+        case DSIM_ST_RANK_DEFICIENT: return "reduced system rank-deficient (redundant contacts)";
+        case DSIM_ST_MODE_DEGENERATE: return "a contact within mode_eps of a mode switch";
+        case DSIM_ST_NONFINITE: return "non-finite value in the outputs";
+        case DSIM_ST_POLISH_FAILED: return "Newton refinement did not reach a consistent mode set";
+        case DSIM_ST_SIZE_EXCEEDED: return "environment larger than the launch's sizes: not computed";
+        case 0: return "ok";
+        default: return "not a single status bit";
     }
 }
 
@@ -463,6 +514,23 @@ int32_t dsim_tangent_to_ambient(const dsim_batch* b, int32_t precision, const vo
         hipLaunchKernelGGL(ambient_kernel<double>, dim3(b->n_env), dim3(64), 0, static_cast<hipStream_t>(stream),
                            view<double>(b), static_cast<const double*>(q), static_cast<const double*>(g_tangent),
                            static_cast<double*>(g_ambient));
+    return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
+}
+
+int32_t dsim_ambient_to_tangent(const dsim_batch* b, int32_t precision, const void* q, const void* g_ambient,
+                                void* g_tangent, void* stream) {
+    if (!b || b->n_env < 0 || (precision != DSIM_F32 && precision != DSIM_F64)) return DSIM_ERR_ARG;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !g_tangent || !g_ambient || !b->body_off || !b->dof_off || !b->cfg_off || !b->jtype)
+        return DSIM_ERR_ARG;
+    if (precision == DSIM_F32)
+        hipLaunchKernelGGL(tangent_kernel<float>, dim3(b->n_env), dim3(64), 0, static_cast<hipStream_t>(stream),
+                           view<float>(b), static_cast<const float*>(q), static_cast<const float*>(g_ambient),
+                           static_cast<float*>(g_tangent));
+    else
+        hipLaunchKernelGGL(tangent_kernel<double>, dim3(b->n_env), dim3(64), 0, static_cast<hipStream_t>(stream),
+                           view<double>(b), static_cast<const double*>(q), static_cast<const double*>(g_ambient),
+                           static_cast<double*>(g_tangent));
     return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
 }
 

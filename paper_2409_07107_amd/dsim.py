@@ -27,7 +27,7 @@ SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim
            "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
            "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params",
-           "dsim_step_jacobian_params")
+           "dsim_step_jacobian_params", "dsim_ambient_to_tangent", "dsim_status_string")
 
 _vp = ctypes.c_void_p
 
@@ -97,6 +97,10 @@ def lib():
         L.dsim_step_integrate_vjp.restype = ctypes.c_int32
         L.dsim_tangent_to_ambient.argtypes = [ctypes.POINTER(CBatch), ctypes.c_int32, _vp, _vp, _vp, _vp]
         L.dsim_tangent_to_ambient.restype = ctypes.c_int32
+        L.dsim_ambient_to_tangent.argtypes = [ctypes.POINTER(CBatch), ctypes.c_int32, _vp, _vp, _vp, _vp]
+        L.dsim_ambient_to_tangent.restype = ctypes.c_int32
+        L.dsim_status_string.argtypes = [ctypes.c_int32]
+        L.dsim_status_string.restype = ctypes.c_char_p
         _LIB = L
     return _LIB
 
@@ -458,6 +462,16 @@ def tangent_to_ambient(db: DeviceBatch, q, g_tangent, out=None):
     if out is None:
         out = torch.empty_like(q)
     _check(lib().dsim_tangent_to_ambient(ctypes.byref(db.c), db.precision, _ptr(q), _ptr(g_tangent), _ptr(out),
+                                         ctypes.c_void_p(_stream())))
+    return out
+
+
+def ambient_to_tangent(db: DeviceBatch, q, g_ambient, out=None):
+    """Gradient on the stored q [sum n_q] -> tangent adjoint [sum n_v]."""
+    import torch
+    if out is None:
+        out = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
+    _check(lib().dsim_ambient_to_tangent(ctypes.byref(db.c), db.precision, _ptr(q), _ptr(g_ambient), _ptr(out),
                                          ctypes.c_void_p(_stream())))
     return out
 

@@ -288,3 +288,61 @@ def test_vjp_with_impulse_adjoint(precision, gpu_lib):
         ((vn * tv).sum() + (lam[:3 * db.n_contact] * tl).sum()).backward()
         torch.cuda.synchronize()
         assert torch.equal(v.grad, o["g_v"]) and torch.equal(tau.grad, o["g_tau"])
+
+
+def test_ambient_and_tangent_maps_are_transposes(gpu_lib):
+    """dsim_ambient_to_tangent after dsim_tangent_to_ambient is the identity,
+    and the ambient-to-tangent map pairs like the differential of q (+) d."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    from oracle.rbd import Model
+    batch = scenes.make("tree36", 4, seed=31)
+    db = _db(batch, 0)
+    rng = np.random.default_rng(5)
+    gt = torch.as_tensor(rng.normal(size=db.n_dof), dtype=db.dtype, device=db.device)
+    back = dsim.ambient_to_tangent(db, db.q, dsim.tangent_to_ambient(db, db.q, gt))
+    ga = torch.as_tensor(rng.normal(size=int(batch.cfg_off[-1])), dtype=db.dtype, device=db.device)
+    gtan = dsim.ambient_to_tangent(db, db.q, ga).cpu().numpy()
+    torch.cuda.synchronize()
+    assert torch.allclose(back, gt, rtol=0, atol=1e-12)
+    gah = ga.cpu().numpy()
+    for e in range(batch.n_env):
+        env = batch.env(e)
+        model = Model(env)
+        c0, c1 = batch.cfg_off[e], batch.cfg_off[e + 1]
+        d0, d1 = batch.dof_off[e], batch.dof_off[e + 1]
+        d = rng.normal(size=d1 - d0)
+        h = 1e-7
+        dq = (model.integrate(env["q"], h * d) - model.integrate(env["q"], -h * d)) / (2 * h)
+        assert abs(gah[c0:c1] @ dq - gtan[d0:d1] @ d) <= 1e-6 * max(1.0, abs(gtan[d0:d1] @ d))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_torch_rollout_with_the_fused_function(precision, gpu_lib):
+    """A rollout written with DiffStepIntegrate and a torch loss on q_T gives
+    the torque gradients of the library's own checkpointed driver."""
+    import torch
+    from paper_2409_07107_amd import dsim, rollout
+    from paper_2409_07107_amd.autograd import diff_step_integrate
+    batch = scenes.make("tree36", 8, seed=32)
+    db = _db(batch, precision)
+    T = 6
+    rng = np.random.default_rng(6)
+    taus = torch.as_tensor(rng.normal(scale=0.5, size=(T, db.n_dof)), dtype=db.dtype, device=db.device)
+    targets = np.stack([batch.q[batch.cfg_off[e]:batch.cfg_off[e] + 3] + 0.05 for e in range(batch.n_env)])
+    c0 = torch.as_tensor(np.asarray(batch.cfg_off[:-1], dtype=np.int64), device=db.device)
+    tgt = torch.as_tensor(targets, dtype=db.dtype, device=db.device)
+    tl = [taus[t].clone().requires_grad_(True) for t in range(T)]
+    q, v = db.q, db.v
+    for t in range(T):
+        q, v = diff_step_integrate(db, q, v, tl[t])
+    p = torch.stack([q[c0 + i] for i in range(3)], 1)
+    loss = ((p - tgt) ** 2).sum()
+    loss.backward()
+    lf = rollout.base_position_loss(db, targets)
+    ref_loss, ref_grad, _ = rollout.rollout_gradient(db, db.q, db.v, taus, lf, checkpoint=3)
+    torch.cuda.synchronize()
+    got = torch.stack([x.grad for x in tl])
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert abs(float(loss) - float(ref_loss.sum())) <= tol * max(1.0, float(loss))
+    assert torch.allclose(got, ref_grad, rtol=tol, atol=tol * float(ref_grad.abs().max()))
