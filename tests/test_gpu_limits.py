@@ -1,0 +1,107 @@
+"""GPU checks at the size limits of the C ABI: the largest tree
+(DSIM_MAX_DOFS = 64 revolute joints) through the step, whose derivative
+launch does not fit a compute unit's LDS and is refused before any launch;
+and the most contacts (DSIM_MAX_CONTACTS = 21, 3 x 21 = 63 impulses, the
+hand-over stride) on a free box, step and Jacobian against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2409_07107_amd import scenes
+from tests.parity_util import TOL, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _chain(nb=64, nc=4, seed=0):
+    rng = np.random.default_rng(seed)
+    bodies = []
+    for k in range(nb):
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        bodies.append(scenes.body(k - 1, scenes.REVOLUTE, axis=ax, jpos=(0, 0, 0.1 if k else 0.0), mass=0.5,
+                                  com=(0, 0, 0.05), inertia=(0.002, 0.002, 0.001, 0, 0, 0)))
+    contacts = [(nb - 1 - c, np.array([0.02 * c, 0.0, 0.1]), 0.6) for c in range(nc)]
+    q = rng.normal(scale=0.2, size=nb)
+    rec = scenes.record(bodies, contacts, q, rng.normal(scale=0.1, size=nb), rng.normal(scale=0.1, size=nb))
+    return scenes.assemble([rec])
+
+
+def _box21(v):
+    b = scenes.body(-1, scenes.FREEFLYER, mass=2.0, inertia=(0.02, 0.03, 0.04, 0, 0, 0))
+    pts = [np.array([x, y, -0.05]) for x in np.linspace(-0.1, 0.1, 7) for y in (-0.06, 0.0, 0.06)]
+    rec = scenes.record([b], [(0, p, 0.5) for p in pts], [0, 0, 0.05, 0, 0, 0, 1.0], v, np.zeros(6))
+    return scenes.assemble([rec])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_largest_tree(precision, gpu_lib):
+    import torch
+    from paper_2409_07107_amd import dsim
+    from oracle.step import forward
+    batch = _chain()
+    assert batch.max_sizes[1] == 64
+    db = dsim.DeviceBatch(batch, precision=precision)
+    out = dsim.step(db)
+    torch.cuda.synchronize()
+    r = forward(batch.env(0))
+    st = int(out["status"][0])
+    say(f"64-dof chain: status {st}, oracle modes {r['modes']}")
+    if not st & 17 and r["info"]["ok"]:
+        v = out["v_next"].double().cpu().numpy()
+        scale = max(np.abs(r["vnext"]).max(), np.abs(batch.v).max(), 9.81 * batch.dt)
+        assert np.abs(v - r["vnext"]).max() / scale <= TOL[precision]["v"]
+    with pytest.raises(dsim.DsimError, match="-2"):
+        dsim.step_jacobian(db)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("v", [[0.0, 0.0, -0.05, 0.0, 0.0, 0.0], [0.4, -0.2, -0.05, 0.0, 0.0, 0.0]])
+def test_most_contacts(precision, v, gpu_lib):
+    """21 coplanar contacts under one box: the impulses are statically
+    indeterminate (rank 6), v+ is unique.  The step is compared on v+; the
+    FP64 derivative launch (63 x 63 FP64 matrices) does not fit the LDS and
+    is refused; the FP32 Jacobian is compared where the modes agree with the
+    oracle's, and otherwise the GPU impulses must solve the oracle's NCP (a
+    different, valid distribution of the load)."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    from oracle import derivative
+    from oracle.step import forward
+    from tests.parity_util import ncp_valid
+    batch = _box21(np.array(v))
+    assert batch.max_sizes[3] == 21
+    db = dsim.DeviceBatch(batch, precision=precision)
+    env = batch.env(0)
+    r = forward(env)
+    tol = TOL[precision]
+    scale = max(np.abs(r["vnext"]).max(), np.abs(batch.v).max(), 9.81 * batch.dt)
+    out = dsim.step(db)
+    torch.cuda.synchronize()
+    st = int(out["status"][0])
+    vn = out["v_next"].double().cpu().numpy()
+    say(f"box with 21 contacts, precision {precision}: status {st}, oracle modes {sorted(set(r['modes']))}")
+    assert np.isfinite(vn).all()
+    if not st & 17:
+        assert np.abs(vn - r["vnext"]).max() / scale <= tol["v"]
+    if precision == 0:
+        with pytest.raises(dsim.DsimError, match="-2"):
+            dsim.step_jacobian(db)
+        return
+    out = dsim.step_jacobian(db)
+    torch.cuda.synchronize()
+    st = int(out["status"][0])
+    if st & 17:
+        say("  solver flagged: Jacobian not compared")
+        return
+    modes = out["mode"][:21].cpu().numpy()
+    if np.array_equal(modes, np.array(r["modes"])):
+        d = derivative.ift(env, r)
+        J = dsim.split_jacobian(db, out, 0)
+        for k in range(3):
+            A, B = J[:, 6 * k:6 * k + 6], d["jac"][:, 6 * k:6 * k + 6]
+            assert np.linalg.norm(A - B) <= tol["jac"] * max(np.linalg.norm(B), 1e-8), k
+        say("  modes agree: Jacobian compared")
+    else:
+        lam = out["lam"][:63].double().cpu().numpy()
+        assert ncp_valid(r["G"], r["g"], r["model"].mu, lam, tol["ncp"])
+        say("  another valid distribution of the impulses: NCP conditions checked")
