@@ -11,8 +11,9 @@ at all.  A plan therefore:
   of `dsim_batch`, no data movement);
 - starts the environments with the highest estimated cost first, a
   longest-processing-time order that shortens the tail of a launch;
-- gives each class the team size (64, 128 or 256 threads) that measured
-  fastest.
+- gives each class the team size (64, 128 or 256 threads, or 0: the
+  library's choice per launch, 128 for the step and 256 for the FP32
+  derivative of large trees) that measured fastest.
 Every launch of a plan goes to one stream, so a plan can be captured once
 as a graph and replayed as a single launch.
 
@@ -33,7 +34,7 @@ import numpy as np
 from . import dsim
 
 LDS_LIMIT = 160 * 1024
-TEAM_SIZES = (64, 128, 256)
+TEAM_SIZES = (0, 64, 128, 256)  # 0: the library's per-launch default
 
 
 def env_sizes(batch):
@@ -205,7 +206,8 @@ def autotune(db, p=None, entry=dsim.ENTRY_JACOBIAN, class_counts=(1, 2, 3, 4, 6)
 
     Candidates: each class count with 128-thread teams (classes whose LDS
     would exceed one compute unit are skipped), then, for the best count,
-    each class's team size tried at 64 and 256 with the others fixed.  A JSON
+    each class's team size tried at 0 (the library's per-launch choice), 64
+    and 256 with the others fixed.  A JSON
     `cache` file maps the batch's size signature to the chosen plan."""
     p = p or db.params()
     sig = signature(db, entry)
