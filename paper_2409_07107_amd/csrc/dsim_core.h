@@ -320,11 +320,14 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.Rw = take<double>(p, 9 * NB, tot);
     E.pw = take<double>(p, 3 * NB, tot);
     E.S = take<double>(p, 6 * NV, tot);
-    E.V = take<double>(p, 6 * NB, tot);
-    E.Acc = take<double>(p, 6 * NB, tot);
-    E.Fc = take<double>(p, 6 * NB, tot);
-    E.Iw = take<double>(p, 10 * NB, tot);
-    E.Ic = take<double>(p, 10 * NB, tot);
+    const bool deriv = entry_has_derivative(entry);
+    if (deriv) {
+        E.V = take<double>(p, 6 * NB, tot);
+        E.Acc = take<double>(p, 6 * NB, tot);
+        E.Fc = take<double>(p, 6 * NB, tot);
+        E.Iw = take<double>(p, 10 * NB, tot);
+        E.Ic = take<double>(p, 10 * NB, tot);
+    }
     E.xw = take<double>(p, 3 * NC, tot);
     E.crad = take<double>(p, NC, tot);
     E.org = take<double>(p, 3, tot);
@@ -345,18 +348,38 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     //    transposed-solve vector; then Q = P M^-1.
     //  * Gd (FP64 G, dead once the reduced system is built) holds Z = A^-1 B,
     //    then T = -K C Z when it fits.
-    //  * step-only entries: the factors of M, then the FP64 product J M^-1;
-    //    M^-1 (dead once J M^-1 is formed), then Gd and A.
+    //  * step-only entries: the factors of M, then the FP64 product J M^-1,
+    //    then (once the Delassus operator is formed) the reduced-system
+    //    matrix A; and one region for the body velocities, accelerations,
+    //    forces and inertias of the dynamics (dead once RNEA and the mass
+    //    matrix are done), then M^-1 (dead once J M^-1 is formed), then Gd
+    //    and G.  Four teams of a 36-dof tree with 8 contacts then fit one
+    //    compute unit's LDS.
     const int NN = NV * NV, KK = K * K;
     const size_t SQ = size_t(KN > KK ? KN : KK);  // doubles of the FP64 product / solve columns
-    const bool deriv = entry_has_derivative(entry);
     double* un = nullptr;
     double* gda = nullptr;
+    double* ax = nullptr;
     if (!deriv) {
-        E.Mx = take<double>(p, size_t(NN > KN ? NN : KN), tot);
+        size_t mx = size_t(NN > K * NV ? NN : K * NV);
+        if (mx < size_t(KK)) mx = size_t(KK);
+        E.Mx = take<double>(p, mx, tot);
         E.scr = E.Mx;
-        gda = take<double>(p, size_t(NN > 2 * KK ? NN : 2 * KK), tot);
-        E.Mi = gda;
+        ax = E.Mx;
+        // Gd, then G in working precision (FP64 runs use Gd itself)
+        const size_t gpair =
+            size_t(KK) + (sizeof(R) == sizeof(double) ? 0 : (size_t(KK) * sizeof(R) + sizeof(double) - 1) / sizeof(double));
+        size_t ur = size_t(38) * NB;
+        if (ur < size_t(NN)) ur = size_t(NN);
+        if (ur < gpair) ur = gpair;
+        double* u = take<double>(p, ur, tot);
+        E.V = u;
+        E.Acc = u + 6 * NB;
+        E.Fc = u + 12 * NB;
+        E.Iw = u + 18 * NB;
+        E.Ic = u + 28 * NB;
+        E.Mi = u;
+        gda = u;
     } else {
         const size_t mxb = size_t(NN) * sizeof(double);
         const size_t czb = entry_is_jacobian(entry) ? size_t(KK > NN ? KK : NN) * sizeof(R) : 0;
@@ -383,7 +406,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     else if (deriv)
         E.G = reinterpret_cast<R*>(un + SQ);
     else
-        E.G = take<R>(p, KK, tot);
+        E.G = reinterpret_cast<R*>(gda + KK);
     E.g = take<R>(p, K, tot);
     E.Lam = take<R>(p, K, tot);
     E.sig = take<R>(p, K, tot);
@@ -397,7 +420,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.Ld = take<double>(p, K, tot);
     E.Ld1 = take<double>(p, K, tot);
     E.dfr = take<double>(p, 4 * NC, tot);
-    E.A = gda ? gda + KK : take<double>(p, KK, tot);
+    E.A = ax ? ax : take<double>(p, KK, tot);
     E.rhs = take<double>(p, K, tot);
     E.X = take<double>(p, K, tot);
     E.ytmp = take<double>(p, K, tot);
