@@ -227,14 +227,18 @@ DSIM_HD inline int local_solve(const R* W, const R* Wi, const R* b, R mu, R* lam
     return SLD;
 }
 
-// `sweeps` block Gauss-Seidel sweeps, run by wavefront 0: sigma = G Lam + g
-// is kept up to date in LDS; each contact update is computed redundantly by
-// all lanes, then the lanes update sigma row-parallel.
+// At most `sweeps` block Gauss-Seidel sweeps, run by wavefront 0: sigma =
+// G Lam + g is kept up to date in LDS; each contact update is computed
+// redundantly by all lanes, then the lanes update sigma row-parallel.  A
+// sweep that changes no impulse and no mode has reached a fixed point in
+// working precision: every further sweep would repeat it exactly, so the
+// sweeps end there (the same result as running them all).
 template <class R>
 DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
     const int k = E.k, nc = E.nc;
     if (T.wave == 0) {
         for (int s = 0; s < sweeps; ++s) {
+            bool moved = false;  // uniform over the wavefront
             for (int c = 0; c < nc; ++c) {
                 const int o = 3 * c;
                 R W[9];
@@ -245,8 +249,11 @@ DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
                 for (int i = 0; i < 3; ++i)
                     b[i] = E.sig[o + i] - (W[3 * i] * L[0] + W[3 * i + 1] * L[1] + W[3 * i + 2] * L[2]);
                 R Ln[3] = {L[0], L[1], L[2]};
-                const int md = local_solve(W, E.Winv + 9 * c, b, E.mu[c], Ln, E.lmode[c]);
+                const int prev = E.lmode[c];
+                const int md = local_solve(W, E.Winv + 9 * c, b, E.mu[c], Ln, prev);
                 const R d0 = Ln[0] - L[0], d1 = Ln[1] - L[1], d2 = Ln[2] - L[2];
+                // NaN differences compare unequal to zero and keep sweeping
+                moved = moved || md != prev || !(d0 == R(0) && d1 == R(0) && d2 == R(0));
                 T.wave_sync();
                 for (int r = T.lane; r < k; r += T.wsize)
                     E.sig[r] += E.G[r * k + o] * d0 + E.G[r * k + o + 1] * d1 + E.G[r * k + o + 2] * d2;
@@ -258,6 +265,7 @@ DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
                 }
                 T.wave_sync();
             }
+            if (!moved) break;
         }
     }
     T.sync();
