@@ -157,8 +157,8 @@ typedef struct dsim_params {
     int32_t ncp_sweeps;   /* block Gauss-Seidel sweeps per round (>= 1) */
     int32_t ncp_rounds;   /* sweep rounds, each followed by Newton refinement */
     int32_t newton_iters; /* Newton iterations per refinement (>= 0) */
-    int32_t threads;      /* threads per environment team: 64, 128 or 256 (0 = auto: 128, and 256 for
-                             the derivative launch of the FP32 form when max_dofs >= 24) */
+    int32_t threads;      /* threads per environment team: 64, 128, 256 or 512 (0 = auto: 128, and
+                             512 for the derivative launch when max_dofs >= 24) */
     double ncp_tol;       /* relative natural-map residual tolerance */
     double rank_tol;      /* relative pivot tolerance of the reduced factorisation */
     double mode_eps;      /* relative threshold of the mode classification */

@@ -12,7 +12,7 @@ at all.  A plan therefore:
 - starts the environments with the highest estimated cost first, a
   longest-processing-time order that shortens the tail of a launch;
 - gives each class the team size (64, 128 or 256 threads, or 0: the
-  library's choice per launch, 128 for the step and 256 for the FP32
+  library's choice per launch, 128 for the step and 512 for the
   derivative of large trees) that measured fastest.
 Every launch of a plan goes to one stream, so a plan can be captured once
 as a graph and replayed as a single launch.

@@ -1,6 +1,6 @@
 // dsim_api.hip -- kernels for gfx950 and the C ABI of include/dsim.h.
 //
-// One workgroup (an "environment team" of 64, 128 or 256 threads) handles one
+// One workgroup (an "environment team" of 64, 128, 256 or 512 threads) handles one
 // environment at a time; its scratch lives in LDS when it fits (160 KB per
 // workgroup on gfx950), otherwise in a caller-provided device workspace.
 #include <hip/hip_runtime.h>
@@ -80,24 +80,24 @@ size_t team_bytes(const dsim_batch* b, const dsim_params* p, int entry) {
     return carve<double>(nullptr, d, entry, E);
 }
 
-// Team size of a launch: the caller's choice, else 128 threads, except 256
-// for the FP32 derivative launch of large trees (24 dofs or more).  The step
+// Team size of a launch: the caller's choice, else 128 threads, except 512
+// for the derivative launch of large trees (24 dofs or more).  The step
 // launch is a chain of dependent small solves in one wavefront per
-// environment, so more threads only add waves that wait; the derivative
-// launch of a large tree in FP32 (one team per compute unit) is dense
-// products that a larger team spreads (measured on tree36 x 16384: 19.0 ms
-// with 128 threads, 15.7 ms with 256; in FP64, and for small trees, the
-// 128-thread team is as fast or faster).
+// environment, so more threads only add waves that wait (and fewer teams fit
+// a compute unit); the derivative launch of a large tree (one team per
+// compute unit, its LDS being the limit) is dense products that a larger team
+// spreads.  Measured on tree36 x 16384: FP32 19.5 ms with 128 threads,
+// 16.4 ms with 256, 14.9 ms with 512; FP64 17.7, 17.0 and 14.8 ms.
 int team_threads(const dsim_params* p, const dsim_batch* b, int entry) {
     if (p->threads > 0) return p->threads;
     const bool big = b->max_dofs >= 24;
-    return (entry_has_derivative(entry) && p->precision == DSIM_F32 && big) ? 256 : 128;
+    return (entry_has_derivative(entry) && big) ? 512 : 128;
 }
 
 // One workgroup (team) per environment; the team's whole working set is
 // carved from the dynamic LDS allocation.
 template <class R, int ENTRY>
-__global__ __launch_bounds__(256) void env_kernel(BatchView<R> B, Params P, Dims D, const R* q, const R* v,
+__global__ __launch_bounds__(512) void env_kernel(BatchView<R> B, Params P, Dims D, const R* q, const R* v,
                                                   const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
                                                   int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, R* o4, R* o5,
                                                   double* ld) {
@@ -350,7 +350,8 @@ int32_t dsim_validate_params(const dsim_params* p) {
     if (p->gap_mode != 0 && p->gap_mode != 1) return DSIM_ERR_ARG;
     if (p->precision != DSIM_F64 && p->precision != DSIM_F32) return DSIM_ERR_ARG;
     if (p->ncp_sweeps < 1 || p->ncp_rounds < 1 || p->newton_iters < 0) return DSIM_ERR_ARG;
-    if (p->threads != 0 && p->threads != 64 && p->threads != 128 && p->threads != 256) return DSIM_ERR_ARG;
+    if (p->threads != 0 && p->threads != 64 && p->threads != 128 && p->threads != 256 && p->threads != 512)
+        return DSIM_ERR_ARG;
     if (!(p->ncp_tol > 0) || !(p->rank_tol > 0) || !(p->mode_eps >= 0)) return DSIM_ERR_ARG;
     if (!(p->kp >= 0 && p->kp <= 1) || !(p->kd >= 0) || !std::isfinite(p->kd)) return DSIM_ERR_ARG;
     return DSIM_SUCCESS;

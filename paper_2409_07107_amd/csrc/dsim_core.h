@@ -56,7 +56,7 @@ struct Team {
 #endif
 };
 
-// Slots of the team reductions: one per wavefront of the largest team (256
+// Slots of the team reductions: one per wavefront of the largest team (512
 // threads); the host build (a debugging build whose team threads are plain
 // threads) uses one per thread.
 #ifdef DSIM_HOST_BUILD
