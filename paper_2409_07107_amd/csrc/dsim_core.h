@@ -184,6 +184,24 @@ struct Dims {
     int NB, NV, NC, K;  // maxima over the batch (K = 3 NC)
 };
 
+// Bitwise equality of two floating-point values (NaN payloads and the sign
+// of zero included).
+template <class T>
+DSIM_HD inline bool same_bits(T a, T b) {
+    if constexpr (sizeof(T) == 4) {
+        uint32_t x, y;
+        __builtin_memcpy(&x, &a, 4);
+        __builtin_memcpy(&y, &b, 4);
+        return x == y;
+    } else {
+        static_assert(sizeof(T) == 8, "float or double");
+        uint64_t x, y;
+        __builtin_memcpy(&x, &a, 8);
+        __builtin_memcpy(&y, &b, 8);
+        return x == y;
+    }
+}
+
 // --------------------------------------------------------------------------
 // small vector helpers (3-vectors, spatial 6-vectors)
 // --------------------------------------------------------------------------
@@ -259,7 +277,7 @@ struct Env {
     int e, b0, d0, q0, c0;  // env index and global offsets
     // small int header: [0] levels, [1] m (reduced size), [2] sticking
     // contacts, [4] rank, [5] status, [6] refinement ok, [9..13] refinement
-    // control, [10] non-finite output
+    // control, [10] non-finite output, [14] sweep state repeated
     int* hdr;
     int *parent, *jtype, *dof0, *ndof, *cfg0, *lorder, *lstart, *dbody, *dpar, *cbody, *cmode, *lmode;
     int *vctc, *vcmp, *rperm, *cperm;  // reduced variables: contact, component; pivots
@@ -273,6 +291,8 @@ struct Env {
     double* scr;  // FP64 solve scratch, max(K, NV) x NV
     // working-precision quantities
     R *mu, *Winv, *J, *KT, *G, *g, *Lam, *sig, *Lam0;
+    R* sig0;      // step entries: sigma and modes at the end of the previous
+    int* lmode0;  // sweep round (with Lam0, the impulses)
     R *dTq, *dTv, *E, *T, *P, *Q;
     // FP64 contact system; reduced variables: row and column vectors, diagonal
     double *vrow, *vcol, *vdiag;
@@ -411,6 +431,13 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.Lam = take<R>(p, K, tot);
     E.sig = take<R>(p, K, tot);
     E.Lam0 = take<R>(p, K, tot);
+    if (!deriv) {
+        E.sig0 = take<R>(p, K, tot);
+        E.lmode0 = take<int>(p, NC, tot);
+    } else {
+        E.sig0 = nullptr;
+        E.lmode0 = nullptr;
+    }
     E.vrow = take<double>(p, 3 * K, tot);
     E.vcol = take<double>(p, 3 * K, tot);
     E.vdiag = take<double>(p, K, tot);

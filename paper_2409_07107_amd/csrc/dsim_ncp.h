@@ -772,8 +772,31 @@ DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P) {
     bool ok = false;
     for (int round = 0; round < P.ncp_rounds && k > 0; ++round) {
         nsgs(T, E, P.ncp_sweeps);
-        for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = double(E.Lam[r]);
-        for (int c = T.tid; c < E.nc; c += T.nt) E.cmode[c] = E.lmode[c];
+        if (round > 0) {
+            // A round whose sweeps end in the state (impulses, sigma, modes)
+            // they ended in the round before repeats that round exactly, its
+            // failed refinement included, and so would every later round: the
+            // solve ends here with the result of running them all.  Compared
+            // bit for bit, so a NaN or a zero of the other sign differs.
+            if (T.tid == 0) {
+                int same = 1;
+                for (int r = 0; r < k; ++r)
+                    same &= (same_bits(E.Lam[r], E.Lam0[r]) && same_bits(E.sig[r], E.sig0[r])) ? 1 : 0;
+                for (int c = 0; c < E.nc; ++c) same &= (E.lmode[c] == E.lmode0[c]) ? 1 : 0;
+                E.hdr[14] = same;
+            }
+            T.sync();
+            if (E.hdr[14]) break;
+        }
+        for (int r = T.tid; r < k; r += T.nt) {
+            E.Ld[r] = double(E.Lam[r]);
+            E.Lam0[r] = E.Lam[r];
+            E.sig0[r] = E.sig[r];
+        }
+        for (int c = T.tid; c < E.nc; c += T.nt) {
+            E.cmode[c] = E.lmode[c];
+            E.lmode0[c] = E.lmode[c];
+        }
         T.sync();
         ok = polish(T, E, P);
         if (ok) break;
