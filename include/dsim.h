@@ -191,12 +191,15 @@ int32_t dsim_validate_host(const dsim_batch* host_batch, int32_t* bad_env);
 int32_t dsim_validate_params(const dsim_params* params);
 
 /* Bytes of device workspace the given entry needs for this batch: 0 for the
- * step entries, n_env * 504 for the derivative entries (Jacobian, VJP and
- * the rollout adjoint), which run as two launches on `stream` -- the step,
- * then the derivative -- and hand the FP64 contact impulses of each
- * environment from the first to the second through the workspace.  Every
- * other quantity stays on chip.  The workspace is the caller's; it must not
- * be shared by calls that may run concurrently. */
+ * step entries; for the derivative entries (Jacobian, VJP, parameter
+ * gradients and the rollout adjoint), which run as two launches on `stream`
+ * -- the step, then the derivative -- the hand-over between them: each
+ * environment's FP64 contact impulses (504 bytes) and a record of the step's
+ * quantities that the derivative reads (kinematics, inertias, M^-1, the
+ * contact rows, the factorised reduced system, v+ and a+), sized by the
+ * batch's max_* fields and the precision (about 36 KB for 31 bodies, 36 dofs
+ * and 8 contacts in FP32).  The workspace is the caller's; it must not be
+ * shared by calls that may run concurrently. */
 size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
 
 /* Bytes of on-chip (LDS) storage one environment team uses for `entry`

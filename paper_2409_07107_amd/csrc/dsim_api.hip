@@ -118,7 +118,7 @@ __global__ __launch_bounds__(512) void env_kernel(BatchView<R> B, Params P, Dims
     }
     Env<R> E;
     carve<R>(smem, D, ENTRY, E);
-    run_env<R>(T, E, B, P, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld);
+    run_env<R>(T, E, B, P, D, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld);
 }
 
 // Tangent gradient on q -> gradient on the stored coordinates of q: per body,
@@ -241,14 +241,20 @@ int launch_one(const dsim_batch* b, const dsim_params* p, const void* q, const v
     return hipGetLastError() == hipSuccess ? DSIM_SUCCESS : DSIM_ERR_LAUNCH;
 }
 
-// Bytes of the impulse hand-over between the step and derivative launches.
-size_t handover_bytes(const dsim_batch* b) { return size_t(b->n_env) * kLdStride * sizeof(double); }
+// Bytes of the hand-over between the step and derivative launches: the FP64
+// impulses, then one record of the step's quantities per environment.
+size_t handover_bytes(const dsim_batch* b, const dsim_params* p) {
+    const Dims d = dims_of(b);
+    const size_t rec = p->precision == DSIM_F32 ? handover_layout<float>(d).bytes : handover_layout<double>(d).bytes;
+    const size_t imp = ((size_t(b->n_env) * kLdStride + 1) & ~size_t(1)) * sizeof(double);
+    return imp + size_t(b->n_env) * rec;
+}
 
 // The step entries are one launch.  A derivative entry is two launches on
 // the same stream: the step (small on-chip footprint, so several teams
 // share a compute unit while they iterate on the contact problem), which
-// also hands its FP64 impulses over through the workspace, then the
-// derivative, which restores the step from them.
+// also hands its FP64 impulses and its other quantities over through the
+// workspace, then the derivative, which loads them.
 template <class R, int ENTRY>
 int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
            const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
@@ -257,7 +263,7 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
     if (!entry_has_derivative(ENTRY))
         return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
                                     nullptr, stream);
-    if (!ws || ws_bytes < handover_bytes(b)) return DSIM_ERR_WORKSPACE;
+    if (!ws || ws_bytes < handover_bytes(b, p)) return DSIM_ERR_WORKSPACE;
     if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
     double* ld = static_cast<double*>(ws);
     int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
@@ -440,7 +446,7 @@ size_t dsim_lds_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) 
 
 size_t dsim_workspace_bytes(const dsim_batch* b, const dsim_params* p, int32_t entry) {
     if (!b || !p || b->n_env <= 0) return 0;
-    return entry_has_derivative(entry) ? handover_bytes(b) : 0;
+    return entry_has_derivative(entry) ? handover_bytes(b, p) : 0;
 }
 
 int32_t dsim_step(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,

@@ -485,4 +485,77 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     return tot;
 }
 
+// --------------------------------------------------------------------------
+// hand-over record of the step launch
+// --------------------------------------------------------------------------
+
+// In a derivative entry the step launch also writes, per environment, the
+// step's quantities that the derivative phases read: placements, motion
+// subspaces, velocities, spatial and composite inertias, contact points,
+// M^-1, the contact rows J and K^T = J M^-1, sigma, the reduced variables and
+// the factorised reduced matrix, v+ and a+.  The derivative launch loads them
+// instead of recomputing the step (the recomputation, latency-bound at one
+// team per compute unit, was most of that launch).  Byte offsets within one
+// record, sized by the launch's maxima.
+struct Handover {
+    size_t Rw, pw, S, V, Iw, Ic, xw, Mi, dsig, vrow, vcol, vdiag, dfr, A, vn, ap, J, KT;
+    size_t rperm, cperm, vctc, vcmp, hdr, bytes;
+};
+
+template <class R>
+DSIM_HD inline Handover handover_layout(const Dims& d) {
+    const size_t NB = d.NB, NV = d.NV, NC = d.NC, K = d.K;
+    Handover h;
+    size_t o = 0;
+    auto at = [&o](size_t bytes) {
+        const size_t r = o;
+        o += (bytes + 15) & ~size_t(15);
+        return r;
+    };
+    const size_t D8 = sizeof(double);
+    h.Rw = at(9 * NB * D8);
+    h.pw = at(3 * NB * D8);
+    h.S = at(6 * NV * D8);
+    h.V = at(6 * NB * D8);
+    h.Iw = at(10 * NB * D8);
+    h.Ic = at(10 * NB * D8);
+    h.xw = at(3 * NC * D8);
+    h.Mi = at(NV * NV * D8);
+    h.dsig = at(K * D8);
+    h.vrow = at(3 * K * D8);
+    h.vcol = at(3 * K * D8);
+    h.vdiag = at(K * D8);
+    h.dfr = at(4 * NC * D8);
+    h.A = at(K * K * D8);
+    h.vn = at(NV * D8);
+    h.ap = at(NV * D8);
+    h.J = at(K * NV * sizeof(R));
+    h.KT = at(K * NV * sizeof(R));
+    h.rperm = at(K * sizeof(int));
+    h.cperm = at(K * sizeof(int));
+    h.vctc = at(K * sizeof(int));
+    h.vcmp = at(K * sizeof(int));
+    h.hdr = at(4 * sizeof(int));
+    h.bytes = o;
+    return h;
+}
+
+// Start of the records in a derivative entry's workspace: after the FP64
+// impulses (kLdStride doubles per environment), 16-byte aligned.
+DSIM_HD inline char* handover_base(double* ld, int n_env) {
+    return reinterpret_cast<char*>(ld + ((size_t(n_env) * kLdStride + 1) & ~size_t(1)));
+}
+
+template <class T>
+DSIM_HD inline void team_put(const Team& Tm, char* rec, size_t off, const T* src, int n) {
+    T* dst = reinterpret_cast<T*>(rec + off);
+    for (int i = Tm.tid; i < n; i += Tm.nt) dst[i] = src[i];
+}
+
+template <class T>
+DSIM_HD inline void team_get(const Team& Tm, const char* rec, size_t off, T* dst, int n) {
+    const T* src = reinterpret_cast<const T*>(rec + off);
+    for (int i = Tm.tid; i < n; i += Tm.nt) dst[i] = src[i];
+}
+
 }  // namespace dsim

@@ -9,29 +9,49 @@
 
 namespace dsim {
 
-// The step: kinematics, dynamics, factorisation, contacts, NCP, v+.
+// The step: kinematics, dynamics, factorisation, contacts, NCP, v+.  With a
+// hand-over record (`rec`, laid out by `H`), each quantity the derivative
+// phases read is also written there once it is final, before its storage
+// is reused.
 template <class R>
-DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q) {
+DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
+                          const Handover* H, char* rec) {
+    const int nb = E.nb, n = E.nv, k = E.k, nc = E.nc;
     kinematics(T, E, B, q);
     mass_matrix(T, E);
     rnea(T, E, P, nullptr, 0.0, E.bias);
+    if (rec) {
+        // the body velocities and inertias share storage with M^-1
+        team_put(T, rec, H->Rw, E.Rw, 9 * nb);
+        team_put(T, rec, H->pw, E.pw, 3 * nb);
+        team_put(T, rec, H->S, E.S, 6 * n);
+        team_put(T, rec, H->V, E.V, 6 * nb);
+        team_put(T, rec, H->Iw, E.Iw, 10 * nb);
+        team_put(T, rec, H->Ic, E.Ic, 10 * nb);
+        team_put(T, rec, H->xw, E.xw, 3 * nc);
+        T.sync();
+    }
     ltdl(T, E);
     tree_inverse(T, E);
     // free motion a_f = M^-1 (tau - b), v_f = v + dt a_f
-    for (int i = T.tid; i < E.nv; i += T.nt) {
+    for (int i = T.tid; i < n; i += T.nt) {
         double s = 0;
-        for (int j = 0; j < E.nv; ++j) s += E.Mi[i * E.nv + j] * (E.tau[j] - E.bias[j]);
+        for (int j = 0; j < n; ++j) s += E.Mi[i * n + j] * (E.tau[j] - E.bias[j]);
         E.af[i] = s;
         E.vf[i] = E.v[i] + P.dt * s;
     }
     T.sync();
-    if (E.k > 0) {
+    if (rec) {
+        // M^-1 shares storage with the Delassus matrices
+        team_put(T, rec, H->Mi, E.Mi, n * n);
+        T.sync();
+    }
+    if (k > 0) {
         contact_jacobian(T, E);
         delassus(T, E, P);
     }
     solve_ncp(T, E, P);
     // v+ = v_f + M^-1 J^T Lam and a+ = a_f + M^-1 J^T Lam / dt
-    const int n = E.nv, k = E.k;
     for (int i = T.tid; i < n; i += T.nt) {
         double s = 0;
         for (int c = 0; c < k; ++c) s += double(E.KT[c * n + i]) * E.Ld[c];
@@ -39,55 +59,71 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
         E.ap[i] = E.af[i] + s / P.dt;
     }
     T.sync();
+    if (rec) {
+        team_put(T, rec, H->J, E.J, k * n);
+        team_put(T, rec, H->KT, E.KT, k * n);
+        team_put(T, rec, H->dsig, E.dsig, k);
+        team_put(T, rec, H->vrow, E.vrow, 3 * k);
+        team_put(T, rec, H->vcol, E.vcol, 3 * k);
+        team_put(T, rec, H->vdiag, E.vdiag, k);
+        team_put(T, rec, H->dfr, E.dfr, 4 * nc);
+        team_put(T, rec, H->A, E.A, k * k);
+        team_put(T, rec, H->vn, E.vn, n);
+        team_put(T, rec, H->ap, E.ap, n);
+        team_put(T, rec, H->rperm, E.rperm, k);
+        team_put(T, rec, H->cperm, E.cperm, k);
+        team_put(T, rec, H->vctc, E.vctc, k);
+        team_put(T, rec, H->vcmp, E.vcmp, k);
+        if (T.tid == 0) {
+            int* h = reinterpret_cast<int*>(rec + H->hdr);
+            h[0] = E.hdr[1];
+            h[1] = E.hdr[2];
+            h[2] = E.hdr[4];
+        }
+    }
     residual_and_flags(T, E, P);
 }
 
-// The step's quantities for the derivative, recomputed from (q, v, tau) with
-// the NCP solution and modes of an earlier step launch: kinematics,
-// dynamics, factorisation, contact rows, then the reduced system at that
-// solution (what the step launch computed, without the solve).
+// The step's quantities for the derivative, loaded from the record the step
+// launch of the same call wrote (its FP64 impulses from `ld`, its modes from
+// `mode`): bit for bit what the step computed.
 template <class R>
-DSIM_HD void restore_step(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
-                          const double* ld, const int8_t* mode) {
-    kinematics(T, E, B, q);
-    mass_matrix(T, E);
-    rnea(T, E, P, nullptr, 0.0, E.bias);
-    ltdl(T, E);
-    tree_inverse(T, E);
-    for (int i = T.tid; i < E.nv; i += T.nt) {
-        double s = 0;
-        for (int j = 0; j < E.nv; ++j) s += E.Mi[i * E.nv + j] * (E.tau[j] - E.bias[j]);
-        E.af[i] = s;
-        E.vf[i] = E.v[i] + P.dt * s;
-    }
-    T.sync();
-    const int n = E.nv, k = E.k;
-    if (k > 0) {
-        contact_jacobian(T, E);
-        delassus(T, E, P);
-    }
+DSIM_HD void load_step(const Team& T, Env<R>& E, const Handover& H, const char* rec, const double* ld,
+                       const int8_t* mode) {
+    const int nb = E.nb, n = E.nv, k = E.k, nc = E.nc;
+    team_get(T, rec, H.Rw, E.Rw, 9 * nb);
+    team_get(T, rec, H.pw, E.pw, 3 * nb);
+    team_get(T, rec, H.S, E.S, 6 * n);
+    team_get(T, rec, H.V, E.V, 6 * nb);
+    team_get(T, rec, H.Iw, E.Iw, 10 * nb);
+    team_get(T, rec, H.Ic, E.Ic, 10 * nb);
+    team_get(T, rec, H.xw, E.xw, 3 * nc);
+    team_get(T, rec, H.Mi, E.Mi, n * n);
+    team_get(T, rec, H.J, E.J, k * n);
+    team_get(T, rec, H.KT, E.KT, k * n);
+    team_get(T, rec, H.dsig, E.dsig, k);
+    team_get(T, rec, H.vrow, E.vrow, 3 * k);
+    team_get(T, rec, H.vcol, E.vcol, 3 * k);
+    team_get(T, rec, H.vdiag, E.vdiag, k);
+    team_get(T, rec, H.dfr, E.dfr, 4 * nc);
+    team_get(T, rec, H.A, E.A, k * k);
+    team_get(T, rec, H.vn, E.vn, n);
+    team_get(T, rec, H.ap, E.ap, n);
+    team_get(T, rec, H.rperm, E.rperm, k);
+    team_get(T, rec, H.cperm, E.cperm, k);
+    team_get(T, rec, H.vctc, E.vctc, k);
+    team_get(T, rec, H.vcmp, E.vcmp, k);
     const double* l = ld + size_t(E.e) * kLdStride;
     for (int r = T.tid; r < k; r += T.nt) {
         E.Ld[r] = l[r];
         E.Lam[r] = R(l[r]);
     }
-    for (int c = T.tid; c < E.nc; c += T.nt) E.cmode[c] = mode[E.c0 + c];
-    T.sync();
-    if (k > 0) {
-        fp64_sigma(T, E);
-        reduced_vars(T, E);
-        build_A(T, E);
-        factor_A(T, E, P.rank_tol);
-    } else if (T.tid == 0) {
-        E.hdr[1] = 0;
-        E.hdr[4] = 0;
-    }
-    T.sync();
-    for (int i = T.tid; i < n; i += T.nt) {
-        double s = 0;
-        for (int c = 0; c < k; ++c) s += double(E.KT[c * n + i]) * E.Ld[c];
-        E.vn[i] = E.vf[i] + s;
-        E.ap[i] = E.af[i] + s / P.dt;
+    for (int c = T.tid; c < nc; c += T.nt) E.cmode[c] = mode[E.c0 + c];
+    if (T.tid == 0) {
+        const int* h = reinterpret_cast<const int*>(rec + H.hdr);
+        E.hdr[1] = h[0];
+        E.hdr[2] = h[1];
+        E.hdr[4] = h[2];
     }
     T.sync();
 }
@@ -865,12 +901,15 @@ DSIM_HD void param_columns(const Team& T, Env<R>& E, const BatchView<R>& B, cons
 // RVJP) run after a step launch over the same environments: they restore
 // the step from `ld` and the written modes, then differentiate it.
 template <class R>
-DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, int entry, int e,
-                     const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
+DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const Dims& D, int entry,
+                     int e, const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
                      int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, R* o4, R* o5, double* ld) {
     load_env(T, E, B, e, q, v, tau);
+    // hand-over record of this environment (derivative entries only)
+    const Handover H = handover_layout<R>(D);
+    char* rec = ld ? handover_base(ld, B.n_env) + size_t(e) * H.bytes : nullptr;
     if (!entry_has_derivative(entry)) {
-        step_forward(T, E, B, P, q);
+        step_forward(T, E, B, P, q, rec ? &H : nullptr, rec);
         write_step(T, E, v_next, lam, mode, status);
         if (ld) {
             double* l = ld + size_t(E.e) * kLdStride;
@@ -878,7 +917,7 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
         }
         if (entry == ENTRY_SINT) integrate(T, E, P, q, o1);
     } else {
-        restore_step(T, E, B, P, q, ld, mode);
+        load_step(T, E, H, rec, ld, mode);
         if (entry == ENTRY_JAC) jacobian(T, E, B, P, o1, o2, o3);
         if (entry == ENTRY_PJAC) {
             jacobian(T, E, B, P, o1, o2, o3);

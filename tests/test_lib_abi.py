@@ -130,15 +130,24 @@ def test_on_chip_sizing(L):
         p = dsim.params(prec)
         lds = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_JACOBIAN)
         assert 0 < lds <= 160 * 1024
-        # the step of a 36-dof tree with 8 contacts leaves room for two or
-        # three teams on one compute unit
+        # the step of a 36-dof tree with 8 contacts leaves room for four
+        # (FP32) or three (FP64) teams on one compute unit
         step = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_STEP)
-        assert step <= 160 * 1024 // (3 if prec == dsim.F32 else 2)
+        assert step <= 160 * 1024 // (4 if prec == dsim.F32 else 3)
         # the derivative entries hand 63 FP64 impulses per environment over
-        # from their step launch; the step entries need no workspace
+        # from their step launch, then one record of the step's quantities
+        # per environment; the step entries need no workspace
+        NB, NV, NQ, NC = b.max_sizes
+        K = 3 * NC
+        r = 4 if prec == dsim.F32 else 8
+        pad = lambda nbytes: (nbytes + 15) // 16 * 16
+        doubles = [9 * NB, 3 * NB, 6 * NV, 6 * NB, 10 * NB, 10 * NB, 3 * NC, NV * NV, K, 3 * K, 3 * K, K, 4 * NC,
+                   K * K, NV, NV]
+        record = sum(pad(8 * x) for x in doubles) + 2 * pad(r * K * NV) + 4 * pad(4 * K) + pad(16)
+        expect = (b.n_env * 63 + 1) // 2 * 2 * 8 + b.n_env * record
         for entry in (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP, dsim.ENTRY_STEP_INTEGRATE_VJP, dsim.ENTRY_VJP_PARAMS,
                       dsim.ENTRY_JACOBIAN_PARAMS):
-            assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 504 * b.n_env
+            assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == expect
         for entry in (dsim.ENTRY_STEP, dsim.ENTRY_STEP_INTEGRATE):
             assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == 0
         # the parameter entries share the on-chip layout of their plain forms
