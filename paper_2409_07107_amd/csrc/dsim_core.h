@@ -318,7 +318,6 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     size_t tot = 0;
     char* p = base;
     const int NB = d.NB, NV = d.NV, NC = d.NC, K = d.K;
-    const int KN = (K > NV ? K : NV) * NV;
     E.hdr = take<int>(p, 16, tot);
     E.parent = take<int>(p, NB, tot);
     E.jtype = take<int>(p, NB, tot);
@@ -359,15 +358,13 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.vn = take<double>(p, NV, tot);
     E.ap = take<double>(p, NV, tot);
     // Buffers with disjoint lifetimes share storage.
-    //  * mx: the factors of M until M^-1 is formed; then (Jacobian) CZ and
-    //    P = I + T J.
-    //  * derivative entries, the union: the FP64 product J M^-1 of the step,
-    //    and beside it G in working precision during the NCP; then the
-    //    per-dof derivative vectors and composites (until dtau/dq, dtau/dv
-    //    and E are formed); then the columns of the reduced solve and the
-    //    transposed-solve vector; then Q = P M^-1.
-    //  * Gd (FP64 G, dead once the reduced system is built) holds Z = A^-1 B,
-    //    then T = -K C Z when it fits.
+    //  * derivative entries (the step's quantities come from the hand-over
+    //    record; M^-1 is read there, in device memory, and not copied):
+    //    mx holds the composites B_b and X_b until dtau/dq, dtau/dv and E
+    //    are formed, then (Jacobian) CZ and P = I + T J; the union holds the
+    //    per-dof derivative vectors, then the columns of the reduced solve
+    //    and the transposed-solve vector, then Q = P M^-1; Gd holds
+    //    Z = A^-1 B, then T = -K C Z when it fits.
     //  * step-only entries: the factors of M, then the FP64 product J M^-1,
     //    then (once the Delassus operator is formed) the reduced-system
     //    matrix A; and one region for the body velocities, accelerations,
@@ -376,7 +373,6 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     //    and G.  Four teams of a 36-dof tree with 8 contacts then fit one
     //    compute unit's LDS.
     const int NN = NV * NV, KK = K * K;
-    const size_t SQ = size_t(KN > KK ? KN : KK);  // doubles of the FP64 product / solve columns
     double* un = nullptr;
     double* gda = nullptr;
     double* ax = nullptr;
@@ -401,17 +397,16 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.Mi = u;
         gda = u;
     } else {
-        const size_t mxb = size_t(NN) * sizeof(double);
+        const size_t cmp = size_t(54) * NB * sizeof(double);
         const size_t czb = entry_is_jacobian(entry) ? size_t(KK > NN ? KK : NN) * sizeof(R) : 0;
-        const size_t b = mxb > czb ? mxb : czb;
+        const size_t b = cmp > czb ? cmp : czb;
         E.Mx = take<double>(p, (b + sizeof(double) - 1) / sizeof(double), tot);
-        E.Mi = take<double>(p, NN, tot);
+        E.Mi = nullptr;  // set to the hand-over record's copy
     }
     if (deriv) {
-        const size_t nvec = size_t(45) * NV + size_t(54) * NB;
-        const size_t gq = (size_t(KK) * sizeof(R) + sizeof(double) - 1) / sizeof(double);
-        size_t u = nvec;
-        if (u < SQ + gq) u = SQ + gq;
+        size_t u = size_t(45) * NV;
+        if (u < size_t(KK)) u = size_t(KK);
+        if (u < size_t(K)) u = size_t(K);
         const size_t qd = (size_t(NN) * sizeof(R) + sizeof(double) - 1) / sizeof(double);
         if (u < qd) u = qd;
         un = take<double>(p, u, tot);
@@ -424,7 +419,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     if (sizeof(R) == sizeof(double))
         E.G = nullptr;  // set to Gd below
     else if (deriv)
-        E.G = reinterpret_cast<R*>(un + SQ);
+        E.G = nullptr;  // the derivative launch forms no Delassus matrix
     else
         E.G = reinterpret_cast<R*>(gda + KK);
     E.g = take<R>(p, K, tot);
@@ -467,8 +462,8 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.cj = d; d += 6 * NV;
         E.Yq = d; d += 6 * NV;
         E.Yv = d; d += 6 * NV;
-        E.Bc = d; d += 36 * NB;
-        E.Ec = d;
+        E.Bc = E.Mx;
+        E.Ec = E.Mx + 36 * NB;
         E.Ysc = un;
         E.Q = reinterpret_cast<R*>(un);
         E.P = reinterpret_cast<R*>(E.Mx);

@@ -98,7 +98,8 @@ DSIM_HD void load_step(const Team& T, Env<R>& E, const Handover& H, const char* 
     team_get(T, rec, H.Iw, E.Iw, 10 * nb);
     team_get(T, rec, H.Ic, E.Ic, 10 * nb);
     team_get(T, rec, H.xw, E.xw, 3 * nc);
-    team_get(T, rec, H.Mi, E.Mi, n * n);
+    // M^-1 is read where the step left it (each entry once per product)
+    E.Mi = reinterpret_cast<double*>(const_cast<char*>(rec) + H.Mi);
     team_get(T, rec, H.J, E.J, k * n);
     team_get(T, rec, H.KT, E.KT, k * n);
     team_get(T, rec, H.dsig, E.dsig, k);

@@ -1,8 +1,9 @@
 """GPU checks at the size limits of the C ABI: the largest tree
-(DSIM_MAX_DOFS = 64 revolute joints) through the step, whose derivative
-launch does not fit a compute unit's LDS and is refused before any launch;
-and the most contacts (DSIM_MAX_CONTACTS = 21, 3 x 21 = 63 impulses, the
-hand-over stride) on a free box, step and Jacobian against the oracle."""
+(DSIM_MAX_DOFS = 64 revolute joints) through the step and, in FP32, the
+Jacobian against the oracle (the FP64 derivative launch does not fit a
+compute unit's LDS and is refused before any launch); and the most contacts
+(DSIM_MAX_CONTACTS = 21, 3 x 21 = 63 impulses, the hand-over stride) on a
+free box, step and Jacobian against the oracle in both forms."""
 import numpy as np
 import pytest
 
@@ -50,8 +51,27 @@ def test_largest_tree(precision, gpu_lib):
         v = out["v_next"].double().cpu().numpy()
         scale = max(np.abs(r["vnext"]).max(), np.abs(batch.v).max(), 9.81 * batch.dt)
         assert np.abs(v - r["vnext"]).max() / scale <= TOL[precision]["v"]
-    with pytest.raises(dsim.DsimError, match="-2"):
-        dsim.step_jacobian(db)
+    if precision == dsim.F64:
+        with pytest.raises(dsim.DsimError, match="-2"):
+            dsim.step_jacobian(db)
+        return
+    from oracle import derivative
+    out = dsim.step_jacobian(db)
+    torch.cuda.synchronize()
+    st = int(out["status"][0])
+    modes = out["mode"][:4].cpu().numpy()
+    assert np.isfinite(dsim.split_jacobian(db, out, 0)).all()
+    if st & 17 or not r["info"]["ok"] or not np.array_equal(modes, np.array(r["modes"])):
+        say(f"  status {st}, modes {modes.tolist()}: Jacobian not compared")
+        return
+    d = derivative.ift(batch.env(0), r)
+    J = dsim.split_jacobian(db, out, 0)
+    n = 64
+    for k in range(3):
+        A, B = J[:, n * k:n * k + n], d["jac"][:, n * k:n * k + n]
+        err = np.linalg.norm(A - B) / max(np.linalg.norm(B), 1e-8)
+        say(f"  block {k}: relative error {err:.2e}")
+        assert err <= TOL[precision]["jac"], k
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -59,10 +79,9 @@ def test_largest_tree(precision, gpu_lib):
 def test_most_contacts(precision, v, gpu_lib):
     """21 coplanar contacts under one box: the impulses are statically
     indeterminate (rank 6), v+ is unique.  The step is compared on v+; the
-    FP64 derivative launch (63 x 63 FP64 matrices) does not fit the LDS and
-    is refused; the FP32 Jacobian is compared where the modes agree with the
-    oracle's, and otherwise the GPU impulses must solve the oracle's NCP (a
-    different, valid distribution of the load)."""
+    Jacobian is compared where the modes agree with the oracle's, and
+    otherwise the GPU impulses must solve the oracle's NCP (a different,
+    valid distribution of the load)."""
     import torch
     from paper_2409_07107_amd import dsim
     from oracle import derivative
@@ -83,10 +102,6 @@ def test_most_contacts(precision, v, gpu_lib):
     assert np.isfinite(vn).all()
     if not st & 17:
         assert np.abs(vn - r["vnext"]).max() / scale <= tol["v"]
-    if precision == 0:
-        with pytest.raises(dsim.DsimError, match="-2"):
-            dsim.step_jacobian(db)
-        return
     out = dsim.step_jacobian(db)
     torch.cuda.synchronize()
     st = int(out["status"][0])
@@ -97,10 +112,17 @@ def test_most_contacts(precision, v, gpu_lib):
     if np.array_equal(modes, np.array(r["modes"])):
         d = derivative.ift(env, r)
         J = dsim.split_jacobian(db, out, 0)
+        err = [np.linalg.norm(J[:, 6 * k:6 * k + 6] - d["jac"][:, 6 * k:6 * k + 6]) /
+               max(np.linalg.norm(d["jac"][:, 6 * k:6 * k + 6]), 1e-8) for k in range(3)]
+        say(f"  modes agree: Jacobian relative errors {', '.join(f'{x:.2e}' for x in err)}")
+        assert np.isfinite(J).all()
+        if st & dsim.ST_MODE_DEGENERATE:
+            # a contact within mode_eps of a mode switch: the one-sided
+            # derivatives differ there, so the comparison is reported only
+            say("  a contact at a mode boundary: reported, not gated")
+            return
         for k in range(3):
-            A, B = J[:, 6 * k:6 * k + 6], d["jac"][:, 6 * k:6 * k + 6]
-            assert np.linalg.norm(A - B) <= tol["jac"] * max(np.linalg.norm(B), 1e-8), k
-        say("  modes agree: Jacobian compared")
+            assert err[k] <= tol["jac"], k
     else:
         lam = out["lam"][:63].double().cpu().numpy()
         assert ncp_valid(r["G"], r["g"], r["model"].mu, lam, tol["ncp"])
