@@ -121,6 +121,28 @@ def test_null_arguments_are_rejected(L):
     assert L.dsim_step_jacobian_params(ctypes.byref(cb), ctypes.byref(p), *([None] * 11), None, 0, None) == -1
 
 
+def test_short_workspace_is_rejected_before_any_launch(L):
+    """A derivative entry checks its workspace against dsim_workspace_bytes
+    on the host and returns DSIM_ERR_WORKSPACE before launching anything (the
+    pointers below are never dereferenced)."""
+    from paper_2409_07107_amd import dsim
+    b = scenes.make("tree36", 3, seed=1)
+    keep = []
+    cb = dsim._host_batch_struct(b, keep)
+    dummy = ctypes.c_void_p(256)
+    for prec in (dsim.F32, dsim.F64):
+        p = dsim.params(prec)
+        need = L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_JACOBIAN)
+        assert need > 504 * b.n_env
+        assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), None, need, None) == -4
+        assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy, need - 1,
+                                    None) == -4
+        # a workspace sized for the impulses alone is too short: the step's
+        # hand-over records follow them
+        assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy,
+                                    504 * b.n_env, None) == -4
+
+
 def test_on_chip_sizing(L):
     from paper_2409_07107_amd import dsim
     b = scenes.make("tree36", 2, seed=1)
