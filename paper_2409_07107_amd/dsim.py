@@ -231,11 +231,13 @@ class DeviceBatch:
         p.kd = float(overrides.get("kd", getattr(self.batch, "kd", 0.0)))
         return p
 
-    def workspace(self, p: CParams, entry: int):
+    def workspace(self, p: CParams, entry: int, cb=None):
         """The workspace of an entry (one per concurrent slot, see
-        private_workspace)."""
+        private_workspace), sized for the launch's batch struct `cb` (a size
+        class of this batch) or for the whole batch."""
         import torch
-        nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(self.c), ctypes.byref(p), int(entry)))
+        c = self.c if cb is None else cb
+        nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(c), ctypes.byref(p), int(entry)))
         if nbytes == 0:
             return None, 0
         key = (self._slot, nbytes)
@@ -286,7 +288,7 @@ def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, ou
     v = db.v if v is None else v
     tau = db.tau if tau is None else tau
     out = out or _outputs(db)
-    ws, nbytes = db.workspace(p, ENTRY_STEP)
+    ws, nbytes = db.workspace(p, ENTRY_STEP, cb)
     _check(lib().dsim_step(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                            _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
                            _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
@@ -305,7 +307,7 @@ def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None =
         out = _outputs(db)
         for k in ("dvdq", "dvdv", "dvdtau"):
             out[k] = torch.empty(max(db.n_jac, 1), dtype=db.dtype, device=db.device)
-    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN)
+    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN, cb)
     _check(lib().dsim_step_jacobian(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                                     _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                     _ptr(out["status"]), _ptr(out["dvdq"]), _ptr(out["dvdv"]),
@@ -327,7 +329,7 @@ def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | No
         out = _outputs(db)
         for k in ("g_q", "g_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
-    ws, nbytes = db.workspace(p, ENTRY_VJP)
+    ws, nbytes = db.workspace(p, ENTRY_VJP, cb)
     _check(lib().dsim_step_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                                _ptr(g_vnext), _ptr(g_lam), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]), _ptr(out["g_tau"]),
@@ -370,7 +372,7 @@ def step_vjp_params(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CPara
         for k in ("g_q", "g_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
         out["g_params"] = torch.empty(max(n_par, 1), dtype=db.dtype, device=db.device)
-    ws, nbytes = db.workspace(p, ENTRY_VJP_PARAMS)
+    ws, nbytes = db.workspace(p, ENTRY_VJP_PARAMS, cb)
     _check(lib().dsim_step_vjp_params(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v),
                                       _ptr(tau), _ptr(g_vnext), _ptr(g_lam), _ptr(out["v_next"]), _ptr(out["lam"]),
                                       _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]),
@@ -401,7 +403,7 @@ def step_jacobian_params(db: DeviceBatch, q=None, v=None, tau=None, p: CParams |
         for k in ("dvdq", "dvdv", "dvdtau"):
             out[k] = torch.empty(max(db.n_jac, 1), dtype=db.dtype, device=db.device)
         out["dvdp"] = torch.empty(max(db.n_pjac, 1), dtype=db.dtype, device=db.device)
-    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN_PARAMS)
+    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN_PARAMS, cb)
     _check(lib().dsim_step_jacobian_params(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q),
                                            _ptr(v), _ptr(tau), _ptr(out["v_next"]), _ptr(out["lam"]),
                                            _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["dvdq"]),
@@ -447,7 +449,7 @@ def step_integrate_vjp(db: DeviceBatch, a_qnext, a_vnext, q=None, v=None, tau=No
         out = _outputs(db)
         for k in ("a_q", "a_v", "g_tau"):
             out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
-    ws, nbytes = db.workspace(p, ENTRY_STEP_INTEGRATE_VJP)
+    ws, nbytes = db.workspace(p, ENTRY_STEP_INTEGRATE_VJP, cb)
     _check(lib().dsim_step_integrate_vjp(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q),
                                          _ptr(v), _ptr(tau), _ptr(a_qnext), _ptr(a_vnext), _ptr(out["v_next"]),
                                          _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
