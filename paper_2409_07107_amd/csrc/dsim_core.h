@@ -415,7 +415,17 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.mu = take<R>(p, NC, tot);
     E.Winv = take<R>(p, 9 * NC, tot);
     E.J = take<R>(p, K * NV, tot);
-    E.KT = take<R>(p, K * NV, tot);
+    // FP64 step entries whose J storage (dead once the Delassus matrix is
+    // formed) holds the reduced matrix A and the reduced-variable vectors:
+    // those live there, and K^T is the FP64 product J M^-1 itself, kept in
+    // mx through the solve
+    const bool in_j = !deriv && sizeof(R) == sizeof(double) && size_t(K) * NV >= size_t(KK) + 7 * size_t(K);
+    if (in_j) {
+        E.KT = reinterpret_cast<R*>(E.Mx);
+        ax = reinterpret_cast<double*>(E.J);
+    } else {
+        E.KT = take<R>(p, K * NV, tot);
+    }
     if (sizeof(R) == sizeof(double))
         E.G = nullptr;  // set to Gd below
     else if (deriv)
@@ -433,9 +443,15 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.sig0 = nullptr;
         E.lmode0 = nullptr;
     }
-    E.vrow = take<double>(p, 3 * K, tot);
-    E.vcol = take<double>(p, 3 * K, tot);
-    E.vdiag = take<double>(p, K, tot);
+    if (in_j) {
+        E.vrow = ax + KK;
+        E.vcol = E.vrow + 3 * K;
+        E.vdiag = E.vcol + 3 * K;
+    } else {
+        E.vrow = take<double>(p, 3 * K, tot);
+        E.vcol = take<double>(p, 3 * K, tot);
+        E.vdiag = take<double>(p, K, tot);
+    }
     E.Gd = gda ? gda : take<double>(p, KK, tot);
     if (sizeof(R) == sizeof(double)) E.G = reinterpret_cast<R*>(E.Gd);
     E.gd = take<double>(p, K, tot);

@@ -50,6 +50,11 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
         contact_jacobian(T, E);
         delassus(T, E, P);
     }
+    if (rec) {
+        // the FP64 solve reuses J's storage
+        team_put(T, rec, H->J, E.J, k * n);
+        T.sync();
+    }
     solve_ncp(T, E, P);
     // v+ = v_f + M^-1 J^T Lam and a+ = a_f + M^-1 J^T Lam / dt
     for (int i = T.tid; i < n; i += T.nt) {
@@ -60,7 +65,6 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
     }
     T.sync();
     if (rec) {
-        team_put(T, rec, H->J, E.J, k * n);
         team_put(T, rec, H->KT, E.KT, k * n);
         team_put(T, rec, H->dsig, E.dsig, k);
         team_put(T, rec, H->vrow, E.vrow, 3 * k);
