@@ -56,13 +56,14 @@ struct Team {
 #endif
 };
 
-// Slots of the team reductions: one per wavefront of the largest team (512
-// threads); the host build (a debugging build whose team threads are plain
-// threads) uses one per thread.
+// Slots of the team reductions: two per wavefront of the largest team (512
+// threads, 8 wavefronts; team_max2 stores a pair per wavefront); the host
+// build (a debugging build whose team threads are plain threads) uses two
+// per thread.
 #ifdef DSIM_HOST_BUILD
-constexpr int kRedSlots = 512;
+constexpr int kRedSlots = 2 * 512;
 #else
-constexpr int kRedSlots = 8;
+constexpr int kRedSlots = 2 * 8;
 #endif
 
 // Maximum of (v, i) over the team: the larger value wins, equal values go to
@@ -302,9 +303,22 @@ struct Env {
     int* redi;
 };
 
+#ifdef DSIM_HOST_BUILD
+// Host build only: when set, every region carve() hands out comes from this
+// allocator with exactly its own size (so that an address checker sees each
+// region's bounds); the byte count is unchanged.
+inline void* (*host_region_alloc)(size_t) = nullptr;
+#endif
+
 template <class T>
 DSIM_HD inline T* take(char*& p, size_t n, size_t& total) {
     size_t bytes = (n * sizeof(T) + 15) & ~size_t(15);
+#ifdef DSIM_HOST_BUILD
+    if (host_region_alloc) {
+        total += bytes;
+        return static_cast<T*>(host_region_alloc(n * sizeof(T)));
+    }
+#endif
     T* r = reinterpret_cast<T*>(p);
     p += bytes;
     total += bytes;

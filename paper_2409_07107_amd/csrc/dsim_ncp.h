@@ -692,11 +692,6 @@ DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
                 E.dsc[0] = nrm;
                 for (int r = 0; r < k; ++r) E.Ld1[r] = E.Ld[r];
             }
-#ifdef DSIM_DEBUG_PRINT
-            printf("refine env %d it %d res %.3e back %d m %d modes", E.e, guard, res, back, m);
-            for (int c = 0; c < nc; ++c) printf(" %d", E.cmode[c]);
-            printf("\n");
-#endif
             int viol = 0;
             // mode inequalities are checked at a solution of the mode
             // equations, or when Newton stalls on the current mode set

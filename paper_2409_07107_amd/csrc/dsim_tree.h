@@ -409,7 +409,9 @@ DSIM_HD void delassus(const Team& T, Env<R>& E, const Params& P) {
         Kd[idx] = s;
     }
     T.sync();
-    for (int idx = T.tid; idx < k * n; idx += T.nt) E.KT[idx] = R(Kd[idx]);
+    // (the FP64 step layout keeps K^T in the product's own storage)
+    if (static_cast<void*>(E.KT) != static_cast<void*>(Kd))
+        for (int idx = T.tid; idx < k * n; idx += T.nt) E.KT[idx] = R(Kd[idx]);
     for (int idx = T.tid; idx < k * k; idx += T.nt) {
         const int a = idx / k, c = idx - a * k;
         if (c > a) continue;

@@ -1,0 +1,78 @@
+"""CPU tests of the library's kernel code compiled for the host
+(tests/host/dsim_host.cpp: the same sources, a team of one thread).
+
+* Every scratch region that carve() hands out gets an allocation of its own
+  of exactly its size, and the whole pipeline (step, Jacobian, parameter
+  VJP and Jacobian, rollout adjoint) runs under AddressSanitizer in both
+  precisions on cubes, tree36, ragged trees and sphere contacts: no region
+  is read or written out of its bounds.  This is the address check of the
+  layout that every kernel carves from LDS (the host build is g++ only; no
+  GPU code is built with a sanitizer).
+* The host build of the FP64 form reproduces the oracle's stored results
+  under the GPU parity gates (the kernel arithmetic itself, checked on the
+  CPU).
+"""
+import os
+import subprocess
+import sys
+import textwrap
+
+import numpy as np
+import pytest
+
+from tests.host import hostsim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def host_lib(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("host") / "libdsim_host.so")
+    return hostsim.HostLib(hostsim.compile_host(out))
+
+
+def test_regions_stay_in_bounds_under_address_checker(tmp_path):
+    lib = str(tmp_path / "libdsim_host_asan.so")
+    hostsim.compile_host(lib, extra=("-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address"))
+    asan = subprocess.run(["g++", "-print-file-name=libasan.so"], check=True, capture_output=True,
+                          text=True).stdout.strip()
+    script = textwrap.dedent(f"""
+        import sys
+        sys.path.insert(0, {ROOT!r})
+        import torch
+        from tests.host.hostsim import HostLib
+        from paper_2409_07107_amd import dsim, scenes
+        H = HostLib({lib!r})
+        entries = (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP_PARAMS, dsim.ENTRY_JACOBIAN_PARAMS,
+                   dsim.ENTRY_STEP_INTEGRATE_VJP, dsim.ENTRY_STEP_INTEGRATE)
+        for name, n in (("cube", 8), ("tree36", 3), ("mixed", 6), ("spheres", 4)):
+            batch = scenes.make(name, n, seed=1)
+            for prec in (1, 0):
+                db = dsim.DeviceBatch(batch, precision=prec, device="cpu")
+                for entry in entries:
+                    g1 = torch.ones(db.n_dof, dtype=db.dtype)
+                    g2 = torch.ones(db.n_dof if entry == dsim.ENTRY_STEP_INTEGRATE_VJP
+                                    else 3 * max(db.n_contact, 1), dtype=db.dtype)
+                    H.run(db, entry, gbar=g1, gbar2=g2, region_alloc=True)
+            print(name, "ok", flush=True)
+    """)
+    env = dict(os.environ, LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    r = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=900)
+    print(r.stdout[-2000:], r.stderr[-4000:])
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert r.stdout.count(" ok") == 4
+
+
+@pytest.mark.parametrize("name", ["cube8", "tree36_24"])
+def test_host_build_fp64_matches_oracle(name, host_lib):
+    from paper_2409_07107_amd import dsim, scenes
+    from tests.parity_util import TOL, compare, load_golden
+    gold = load_golden(name)
+    batch = scenes.make(str(gold["workload"]), int(gold["n_env"]), seed=int(gold["seed"]))
+    db = dsim.DeviceBatch(batch, precision=dsim.F64, device="cpu")
+    out = host_lib.run(db, dsim.ENTRY_JACOBIAN)
+    st = compare(batch, gold, out, db, 0, label=f"host {name}")
+    assert st["included"] >= max(1, st["n"] // 3)  # the gate of the GPU parity test
+    assert st["v_max"] <= TOL[0]["v"]
+    assert st["jac_max"] <= TOL[0]["jac"]
+    assert st["modes_agree"] == st["included"]
