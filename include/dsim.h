@@ -155,7 +155,10 @@ typedef struct dsim_params {
                              plus the Baumgarte terms of kp, kd (Appendix D) */
     int32_t precision;    /* dsim_precision */
     int32_t ncp_sweeps;   /* block Gauss-Seidel sweeps per round (>= 1) */
-    int32_t ncp_rounds;   /* sweep rounds, each followed by Newton refinement */
+    int32_t ncp_rounds;   /* sweep rounds of the solve's first pass, each followed by
+                             Newton refinement; an environment they leave unsolved
+                             goes to the fallback pass (damped Newton on the
+                             natural map, then ADMM, in FP64; Section II.B) */
     int32_t newton_iters; /* Newton iterations per refinement (>= 0) */
     int32_t threads;      /* threads per environment team: 64, 128, 256 or 512 (0 = auto: 128, and
                              512 for the derivative launch when max_dofs >= 24) */
@@ -211,6 +214,10 @@ size_t dsim_lds_bytes(const dsim_batch* batch, const dsim_params* params, int32_
  * The step (eq. 3-5 and the NCP).  Inputs q [sum n_q], v [sum n_v],
  * tau [sum n_v]; outputs v_next [sum n_v], lam [3 * sum n_c] (impulses,
  * (T1 T2 N) per contact), mode [sum n_c] (DSIM_MODE_*), status [n_env].
+ * Runs as two launches on `stream`: the solve's first pass over every
+ * environment, then its fallback pass, which reads the first pass's lam and
+ * status for the environments left unsolved (so the output buffers must not
+ * alias the inputs).
  */
 int32_t dsim_step(const dsim_batch* batch, const dsim_params* params,
                   const void* q, const void* v, const void* tau,

@@ -19,12 +19,17 @@ derivative only depends on the solution):
   2. Newton iterations on the equations of the realised modes (Section III.B:
      breaking Lam = 0, sticking sigma = 0, sliding sigma_N = 0 and
      Lam_T = -mu Lam_N sigma_T / |sigma_T|);
-  3. a check of every NCP condition.
+  3. a check of every NCP condition;
+  4. when these do not finish, Levenberg-Marquardt on the natural map from
+     the sweeps' iterate, then ADMM (named in Section II.B) followed by it.
 For at most three contacts, `enumerate_solutions` tries every assignment of
 modes and keeps each consistent solution (brute force).
 
-Pins (tests/test_oracle_ncp.py): single-contact closed forms for every mode,
-the conditions at every returned solution, agreement with brute force.
+Pins (tests/test_oracle_ncp.py, tests/test_oracle_pins.py): single-contact
+closed forms for every mode, the conditions at every returned solution,
+agreement with brute force, `check` rejecting each violated condition, the
+natural-map Jacobian against central differences, the fallbacks' solutions
+against brute force.
 """
 from __future__ import annotations
 
@@ -309,8 +314,151 @@ def active_set(G, g, mu, Lam, modes, max_changes=30):
     return None
 
 
+# ---------------------------------------------------------------------------
+# fallbacks: damped Newton on the natural map, ADMM
+# ---------------------------------------------------------------------------
+
+def project_cone_jacobian(x, mu):
+    """Derivative of `project_cone` at x (a generalised one on the cone's
+    boundary rays): the identity inside K_mu, zero inside its polar cone,
+    else the derivative of beta (mu x_T / |x_T|, 1) with
+    beta = (mu |x_T| + x_N) / (mu^2 + 1)."""
+    xt, xn = x[:2], x[2]
+    nt = np.hypot(xt[0], xt[1])
+    if nt <= mu * xn:
+        return np.eye(3)
+    if mu * nt <= -xn:
+        return np.zeros((3, 3))
+    t = xt / nt
+    beta = (mu * nt + xn) / (mu * mu + 1.0)
+    dbeta = np.r_[mu * t, 1.0] / (mu * mu + 1.0)   # d beta / d x
+    D = np.zeros((3, 3))
+    D[:2, :] = mu * np.outer(t, dbeta)
+    D[:2, :2] += mu * beta * (np.eye(2) - np.outer(t, t)) / nt
+    D[2, :] = dbeta
+    return D
+
+
+def natural_map(G, g, mu, Lam):
+    """F(Lam)_i = Lam_i - P_K(Lam_i - rho_i (sigma_i + Gamma(sigma_i))), the
+    map whose zeros are the NCP solutions (the norms of its blocks are
+    `natural_residual`), and a generalised Jacobian of it (chain rule with
+    `project_cone_jacobian`; d|sigma_T| / d sigma_T = sigma_T / |sigma_T|,
+    taken 0 at sigma_T = 0)."""
+    nc = len(mu)
+    k = 3 * nc
+    sig = G @ Lam + g
+    F = np.zeros(k)
+    JF = np.zeros((k, k))
+    for i in range(nc):
+        s = slice(3 * i, 3 * i + 3)
+        tr = np.trace(G[s, s])
+        rho = 3.0 / tr if tr > 0 else 1.0
+        y = Lam[s] - rho * desaxce(sig[s], mu[i])
+        F[s] = Lam[s] - project_cone(y, mu[i])
+        nt = np.hypot(sig[3 * i], sig[3 * i + 1])
+        dGamma = np.eye(3)        # d (sigma + Gamma(sigma)) / d sigma
+        if nt > 0:
+            dGamma[2, :2] = mu[i] * sig[3 * i:3 * i + 2] / nt
+        dy = -rho * dGamma @ G[s, :]
+        dy[:, s] += np.eye(3)
+        JF[s, :] = -project_cone_jacobian(y, mu[i]) @ dy
+        JF[s, s] += np.eye(3)
+    return F, JF
+
+
+def levenberg_marquardt(G, g, mu, Lam, iters=200, tol=1e-13):
+    """Damped Gauss-Newton (Levenberg-Marquardt) on |F(Lam)|^2 for the
+    natural map F: steps d = -(H + lam diag(H))^-1 J^T F with H = J^T J,
+    taken when they decrease |F|, else the damping grows.  Needs no mode set;
+    tolerates the singular J of redundant contacts.  Returns (Lam, ok) with
+    ok when max_i |F_i| <= tol max(|Lam|_inf, s), s = max_i rho_i |g_i| the
+    impulse that stops the free motion (the scale when every contact
+    separates and Lam = 0)."""
+    Lam = Lam.copy()
+    nc = len(mu)
+    s_imp = max([3.0 / np.trace(G[3 * i:3 * i + 3, 3 * i:3 * i + 3]) * np.linalg.norm(g[3 * i:3 * i + 3])
+                 for i in range(nc) if np.trace(G[3 * i:3 * i + 3, 3 * i:3 * i + 3]) > 0] + [1e-300])
+    F, JF = natural_map(G, g, mu, Lam)
+    f = F @ F
+    lam = 1e-3
+    for _ in range(iters):
+        scale = max(np.abs(Lam).max(), s_imp)
+        if np.linalg.norm(F.reshape(-1, 3), axis=1).max() <= tol * scale:
+            return Lam, True
+        H = JF.T @ JF
+        b = -JF.T @ F
+        while True:
+            Hd = H + lam * (np.diag(np.diag(H)) + 1e-12 * np.trace(H) / len(Lam) * np.eye(len(Lam)))
+            try:
+                d = np.linalg.solve(Hd, b)
+            except np.linalg.LinAlgError:
+                d = None
+            if d is not None:
+                Fn, Jn = natural_map(G, g, mu, Lam + d)
+                if np.all(np.isfinite(Fn)) and Fn @ Fn < f:
+                    Lam, F, JF, f = Lam + d, Fn, Jn, Fn @ Fn
+                    lam = max(lam / 3.0, 1e-12)
+                    break
+            lam *= 4.0
+            if lam > 1e12:
+                return Lam, False
+    scale = max(np.abs(Lam).max(), s_imp)
+    return Lam, bool(np.linalg.norm(F.reshape(-1, 3), axis=1).max() <= tol * scale)
+
+
+def admm(G, g, mu, iters=5000, tol=1e-8):
+    """ADMM (one of the NCP solvers Section II.B names) on the De Saxce form:
+    with s = Gamma(sigma) held fixed the NCP is the optimality condition of
+    min 1/2 Lam^T G Lam + (g + s)^T Lam over the cone product; the splitting
+    Lam = z with penalty rho = trace(G)/k alternates the unconstrained
+    minimiser, the cone projection and the multiplier update, and s follows
+    sigma at z.  Returns (z, ok) with ok when the natural residual is at most
+    tol max |z|."""
+    nc = len(mu)
+    k = 3 * nc
+    rho = np.trace(G) / k if np.trace(G) > 0 else 1.0
+    Minv = np.linalg.inv(G + rho * np.eye(k))
+    z = np.zeros(k)
+    u = np.zeros(k)
+    s = np.zeros(k)
+    for it in range(iters):
+        lam = Minv @ (rho * (z - u) - g - s)
+        y = lam + u
+        z = np.concatenate([project_cone(y[3 * i:3 * i + 3], mu[i]) for i in range(nc)])
+        u = u + lam - z
+        sig = G @ z + g
+        s = np.zeros(k)
+        s[2::3] = mu * np.hypot(sig[0::3], sig[1::3])
+        if it % 20 == 19 and natural_residual(G, g, mu, z).max() <= tol * max(np.abs(z).max(), 1e-300):
+            return z, True
+    return z, False
+
+
+def _accept_fallback(G, g, mu, lam):
+    """A fallback solution is taken when it meets every NCP condition and the
+    natural-map tolerance; Newton on its classified modes then polishes it to
+    rounding level when that keeps both."""
+    scale = max(np.abs(lam).max(), 1e-300)
+    if not (check(G, g, mu, lam, tol=1e-11) and natural_residual(G, g, mu, lam).max() <= 1e-11 * scale):
+        return None
+    modes, _ = classify(G, g, mu, lam)
+    pol = newton_modes(G, g, mu, lam, modes)
+    ps = max(np.abs(pol).max(), 1e-300)
+    if check(G, g, mu, pol, tol=1e-11) and natural_residual(G, g, mu, pol).max() <=             min(1e-11 * ps, natural_residual(G, g, mu, lam).max()):
+        return pol
+    return lam
+
+
 def solve(G, g, mu, tol=1e-12, max_sweeps=2000, Lam0=None):
-    """Solve the NCP. Returns (Lam, info)."""
+    """Solve the NCP. Returns (Lam, info).
+
+    Block Gauss-Seidel sweeps in chunks, each chunk followed by Newton on
+    the realised modes and an active-set search; after the first chunk that
+    these do not finish, a damped Newton iteration on the natural map from
+    the sweeps' iterate, then ADMM followed by it (the solvers of
+    Section II.B are interchangeable: the derivative depends on the solution
+    only)."""
     nc = len(mu)
     k = 3 * nc
     Lam = np.zeros(k) if Lam0 is None else Lam0.copy()
@@ -344,6 +492,17 @@ def solve(G, g, mu, tol=1e-12, max_sweeps=2000, Lam0=None):
         if cand is not None:
             info.update(sweeps=sweeps_done, polished=True, ok=True, active_set=True)
             return cand, info
+        if not info.get("fallback_tried"):
+            info["fallback_tried"] = True
+            cand, ok = levenberg_marquardt(G, g, mu, Lam)
+            cand = _accept_fallback(G, g, mu, cand) if ok else None
+            if cand is None:
+                z, _ = admm(G, g, mu)
+                cand, ok = levenberg_marquardt(G, g, mu, z)
+                cand = _accept_fallback(G, g, mu, cand) if ok else None
+            if cand is not None:
+                info.update(sweeps=sweeps_done, polished=True, ok=True, fallback=True)
+                return cand, info
         chunk = min(2 * chunk, 2000)
     info.update(sweeps=sweeps_done, ok=check(G, g, mu, Lam, tol=1e-6))
     return Lam, info

@@ -3,7 +3,8 @@
     python -m paper_2409_07107_amd.build
 
 Compiles csrc/dsim_api.hip with hipcc for gfx950 only.  Packed FP32
-instructions are disabled (-packed-fp32-ops).
+instructions are disabled (-packed-fp32-ops), and so is one backend pass
+that miscompiles this source (see `command`).
 """
 from __future__ import annotations
 
@@ -28,8 +29,14 @@ def hipcc() -> str:
 
 
 def command(out: str = LIB, extra=()) -> list:
+    # -amdgpu-enable-rewrite-partial-reg-uses=false: with that backend pass
+    # on, some inlining outcomes of this source end in a machine-verifier
+    # error ("Illegal instruction detected: Operand has incorrect register
+    # class" on a compare against the private aperture base) at -O3; the pass
+    # only narrows register classes, so turning it off changes no arithmetic.
     return [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-enable-rewrite-partial-reg-uses=false",
             "-I", os.path.join(ROOT, "include"),
             *extra, *SOURCES, "-o", out]
 

@@ -58,6 +58,7 @@ Params params_of(const dsim_params* p) {
     q.mode_eps = p->mode_eps;
     q.kp = p->kp;
     q.kd = p->kd;
+    q.pass = 0;
     return q;
 }
 
@@ -116,6 +117,9 @@ __global__ __launch_bounds__(512) void env_kernel(BatchView<R> B, Params P, Dims
         if (threadIdx.x == 0) status[e] = ST_SIZE;
         return;
     }
+    // the fallback pass of the solve recomputes only the environments the
+    // first pass left unsolved (the whole workgroup exits for the others)
+    if (P.pass == 1 && !(status[e] & (ST_NCP | ST_POLISH))) return;
     Env<R> E;
     carve<R>(smem, D, ENTRY, E);
     run_env<R>(T, E, B, P, D, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld);
@@ -220,7 +224,7 @@ int check_common(const dsim_batch* b, const dsim_params* p) {
 template <class R, int ENTRY>
 int launch_one(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
                const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status,
-               void* o1, void* o2, void* o3, void* o4, void* o5, double* ld, void* stream) {
+               void* o1, void* o2, void* o3, void* o4, void* o5, double* ld, void* stream, int pass = 0) {
     const size_t bytes = team_bytes(b, p, ENTRY);
     if (bytes > kLdsLimit) return DSIM_ERR_SIZE;  // the team's working set must fit in LDS
     const int threads = team_threads(p, b, ENTRY);
@@ -233,8 +237,10 @@ int launch_one(const dsim_batch* b, const dsim_params* p, const void* q, const v
     }
     const int grid = b->order ? b->n_order : b->n_env;
     if (grid <= 0) return DSIM_SUCCESS;
+    Params P = params_of(p);
+    P.pass = pass;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, static_cast<hipStream_t>(stream), view<R>(b),
-                       params_of(p), dims_of(b), static_cast<const R*>(q), static_cast<const R*>(v),
+                       P, dims_of(b), static_cast<const R*>(q), static_cast<const R*>(v),
                        static_cast<const R*>(tau), static_cast<const R*>(gbar), static_cast<const R*>(gbar2),
                        static_cast<R*>(v_next), static_cast<R*>(lam), mode, status, static_cast<R*>(o1),
                        static_cast<R*>(o2), static_cast<R*>(o3), static_cast<R*>(o4), static_cast<R*>(o5), ld);
@@ -250,25 +256,36 @@ size_t handover_bytes(const dsim_batch* b, const dsim_params* p) {
     return imp + size_t(b->n_env) * rec;
 }
 
-// The step entries are one launch.  A derivative entry is two launches on
-// the same stream: the step (small on-chip footprint, so several teams
-// share a compute unit while they iterate on the contact problem), which
-// also hands its FP64 impulses and its other quantities over through the
-// workspace, then the derivative, which loads them.
+// The step is two launches of the step kernel on the same stream: the first
+// pass of the solve over every environment, then its fallback pass, whose
+// workgroups exit at once for the environments the first pass solved (its
+// status output tells them) and recompute the others from the first pass's
+// impulses.  A hard environment's fallback then overlaps with the others'
+// instead of lengthening one team's chain of rounds.  A derivative entry
+// adds a third launch: the step launches have a small on-chip footprint
+// (several teams share a compute unit while they iterate on the contact
+// problem) and hand their FP64 impulses and other quantities over through
+// the workspace to the derivative launch, which loads them.
 template <class R, int ENTRY>
 int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
            const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
            void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream) {
     if (b->n_env == 0) return DSIM_SUCCESS;
-    if (!entry_has_derivative(ENTRY))
+    if (!entry_has_derivative(ENTRY)) {
+        int rc = launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
+                                      nullptr, stream, 0);
+        if (rc) return rc;
         return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
-                                    nullptr, stream);
+                                    nullptr, stream, 1);
+    }
     if (!ws || ws_bytes < handover_bytes(b, p)) return DSIM_ERR_WORKSPACE;
     if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
     double* ld = static_cast<double*>(ws);
-    int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
-                                       nullptr, nullptr, nullptr, nullptr, ld, stream);
-    if (rc) return rc;
+    for (int pass = 0; pass < 2; ++pass) {
+        int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                           nullptr, nullptr, nullptr, nullptr, ld, stream, pass);
+        if (rc) return rc;
+    }
     return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld,
                                 stream);
 }
@@ -302,7 +319,7 @@ void dsim_default_params(dsim_params* p, int32_t precision) {
     p->gap_mode = 0;
     p->precision = precision;
     p->ncp_sweeps = 30;
-    p->ncp_rounds = 8;
+    p->ncp_rounds = 4;
     p->newton_iters = 6;
     p->threads = 0;
     if (precision == DSIM_F32) {

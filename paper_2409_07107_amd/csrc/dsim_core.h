@@ -26,13 +26,19 @@
 #include <cmath>
 #include <cstdio>
 #define DSIM_HD
+#define DSIM_INLINE inline
 using std::cos;
 using std::fabs;
 using std::sin;
 using std::sqrt;
 #else
 #include <hip/hip_runtime.h>
-#define DSIM_HD __host__ __device__
+// Every per-environment function is inlined into its kernel: a function
+// compiled on its own sees the LDS buffers behind Env's pointers as generic
+// (flat) addresses and reaches LDS with flat loads and stores, several times
+// slower than the LDS instructions the kernel body gets.
+#define DSIM_HD __host__ __device__ __attribute__((always_inline))
+#define DSIM_INLINE inline
 #endif
 
 namespace dsim {
@@ -56,14 +62,14 @@ struct Team {
 #endif
 };
 
-// Slots of the team reductions: two per wavefront of the largest team (512
-// threads, 8 wavefronts; team_max2 stores a pair per wavefront); the host
-// build (a debugging build whose team threads are plain threads) uses two
-// per thread.
+// Slots of the team reductions: three per wavefront of the largest team
+// (512 threads, 8 wavefronts; team_max2 stores a pair per wavefront and the
+// natural map's sum one more); the host build (a debugging build whose team
+// threads are plain threads) uses two per thread.
 #ifdef DSIM_HOST_BUILD
 constexpr int kRedSlots = 2 * 512;
 #else
-constexpr int kRedSlots = 2 * 8;
+constexpr int kRedSlots = 3 * 8;
 #endif
 
 // Maximum of (v, i) over the team: the larger value wins, equal values go to
@@ -179,6 +185,7 @@ struct Params {
     int gap_mode, ncp_sweeps, ncp_rounds, newton_iters;
     double ncp_tol, rank_tol, mode_eps;
     double kp, kd;  // Baumgarte gains (gap mode 1)
+    int pass;       // step launches: 0 the first pass, 1 the fallback pass of the solve
 };
 
 struct Dims {
@@ -299,6 +306,7 @@ struct Env {
     double *vrow, *vcol, *vdiag;
     double *Gd, *gd, *Ld, *Ld1, *dfr;
     double *A, *Z, *Ysc, *rhs, *X, *ytmp, *dsig, *dsc;
+    double* A2;  // step entries: a second k x k FP64 matrix for the damped Newton fallback of the solve
     double* redv;  // team reductions: one (value, index) slot per wavefront
     int* redi;
 };
@@ -390,9 +398,17 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     double* un = nullptr;
     double* gda = nullptr;
     double* ax = nullptr;
+    // FP64 step entries whose J storage (dead once the Delassus matrix is
+    // formed) holds the reduced matrix A and the reduced-variable vectors:
+    // those live there, and K^T is the FP64 product J M^-1 itself, kept in
+    // mx through the solve
+    const bool in_j = !deriv && sizeof(R) == sizeof(double) && size_t(K) * NV >= size_t(KK) + 7 * size_t(K);
     if (!deriv) {
         size_t mx = size_t(NN > K * NV ? NN : K * NV);
         if (mx < size_t(KK)) mx = size_t(KK);
+        // the fallback's second k x k matrix follows A in mx, or (J layout)
+        // Gd in the shared region
+        if (!in_j && mx < size_t(2) * KK) mx = size_t(2) * KK;
         E.Mx = take<double>(p, mx, tot);
         E.scr = E.Mx;
         ax = E.Mx;
@@ -402,6 +418,7 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         size_t ur = size_t(38) * NB;
         if (ur < size_t(NN)) ur = size_t(NN);
         if (ur < gpair) ur = gpair;
+        if (in_j && ur < size_t(2) * KK) ur = size_t(2) * KK;
         double* u = take<double>(p, ur, tot);
         E.V = u;
         E.Acc = u + 6 * NB;
@@ -429,11 +446,6 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.mu = take<R>(p, NC, tot);
     E.Winv = take<R>(p, 9 * NC, tot);
     E.J = take<R>(p, K * NV, tot);
-    // FP64 step entries whose J storage (dead once the Delassus matrix is
-    // formed) holds the reduced matrix A and the reduced-variable vectors:
-    // those live there, and K^T is the FP64 product J M^-1 itself, kept in
-    // mx through the solve
-    const bool in_j = !deriv && sizeof(R) == sizeof(double) && size_t(K) * NV >= size_t(KK) + 7 * size_t(K);
     if (in_j) {
         E.KT = reinterpret_cast<R*>(E.Mx);
         ax = reinterpret_cast<double*>(E.J);
@@ -473,11 +485,12 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     E.Ld1 = take<double>(p, K, tot);
     E.dfr = take<double>(p, 4 * NC, tot);
     E.A = ax ? ax : take<double>(p, KK, tot);
+    E.A2 = deriv ? nullptr : (in_j ? E.Gd + KK : E.Mx + KK);
     E.rhs = take<double>(p, K, tot);
     E.X = take<double>(p, K, tot);
     E.ytmp = take<double>(p, K, tot);
     E.dsig = take<double>(p, K, tot);
-    E.dsc = take<double>(p, 8, tot);
+    E.dsc = take<double>(p, 12, tot);
     E.redv = take<double>(p, kRedSlots, tot);
     E.redi = take<int>(p, kRedSlots, tot);
     if (deriv) {

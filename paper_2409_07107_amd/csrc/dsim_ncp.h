@@ -12,6 +12,11 @@
 
 namespace dsim {
 
+// Iteration caps of the solve's fallback pass: damped Newton on the
+// natural map, ADMM.
+constexpr int kLmIters = 40;
+constexpr int kAdmmIters = 1500;
+
 // Unit slip direction t solving (s I + r Wt) t = bt for s > 0, with Wt given
 // by its eigen-decomposition (l1 >= l2 >= 0, unit eigenvector (e0, e1) of l1)
 // and bt by its coordinates beta in that basis.  |t(s)| decreases in s;
@@ -407,7 +412,7 @@ DSIM_HD void build_A(const Team& T, Env<R>& E) {
 // and U in A, the row and column permutations in rperm/cperm, the rank in
 // hdr[4].
 template <class R>
-DSIM_HD void factor_A(const Team& T, Env<R>& E, double rank_tol) {
+DSIM_INLINE DSIM_HD void factor_A(const Team& T, Env<R>& E, double rank_tol) {
     const int m = E.hdr[1];
     const int nst = 3 * E.hdr[2];
     double* A = E.A;
@@ -540,7 +545,7 @@ DSIM_HD inline void lu_solve(const double* A, int m, int rank, const int* rperm,
 // and dsc[3] its squared 2-norm (velocity rows scaled by the free-velocity
 // scale, impulse rows by the impulse scale).  Uses Ld and dsig.
 template <class R>
-DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
+DSIM_INLINE DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
     const int k = E.k, nc = E.nc;
     // unknowns: every thread counts the active contacts (sticking first,
     // then sliding) and thread c fills the slots of contact c
@@ -662,7 +667,7 @@ DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
 // stalled than with the nearly plain Newton step).  Returns true on a
 // consistent solution.
 template <class R>
-DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
+DSIM_INLINE DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
     const int k = E.k, nc = E.nc;
     const int max_changes = 2 * nc + 2;
     int changes = 0, since = 0;
@@ -752,20 +757,482 @@ DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
     return ok;
 }
 
-// The NCP: sweeps in working precision, refinement in FP64, repeated in
-// rounds until the refinement reaches a consistent solution; then the
-// paper's reduced system at the solution, factorised for the derivative.
+// --------------------------------------------------------------------------
+// damped semismooth Newton on the natural map (the fallback of the solve)
+// --------------------------------------------------------------------------
+
+// Projection of y onto the friction cone K_mu = {|x_T| <= mu x_N} and its
+// Jacobian Pm (row-major 3x3): the identity inside the cone, zero in its
+// polar cone, else the derivative of the boundary point
+// beta (mu t, 1), beta = (mu |y_T| + y_N) / (mu^2 + 1), t = y_T / |y_T|.
+DSIM_HD inline void cone_proj_jac(const double* y, double mu, double* p, double* Pm) {
+    const double nt = sqrt(y[0] * y[0] + y[1] * y[1]);
+    for (int i = 0; i < 9; ++i) Pm[i] = 0.0;
+    if (nt <= mu * y[2]) {
+        p[0] = y[0];
+        p[1] = y[1];
+        p[2] = y[2];
+        Pm[0] = Pm[4] = Pm[8] = 1.0;
+        return;
+    }
+    if (mu * nt <= -y[2]) {
+        p[0] = p[1] = p[2] = 0.0;
+        return;
+    }
+    const double c = 1.0 / (mu * mu + 1.0);
+    const double beta = (mu * nt + y[2]) * c;
+    const double t0 = y[0] / nt, t1 = y[1] / nt;
+    const double db[3] = {c * mu * t0, c * mu * t1, c};
+    const double h = mu * beta / nt;
+    p[0] = mu * beta * t0;
+    p[1] = mu * beta * t1;
+    p[2] = beta;
+    for (int j = 0; j < 3; ++j) {
+        Pm[j] = mu * t0 * db[j];
+        Pm[3 + j] = mu * t1 * db[j];
+        Pm[6 + j] = db[j];
+    }
+    Pm[0] += h * (1.0 - t0 * t0);
+    Pm[1] -= h * t0 * t1;
+    Pm[3] -= h * t0 * t1;
+    Pm[4] += h * (1.0 - t1 * t1);
+}
+
+// Sum and maximum over the wavefront (every lane gets the result; the host
+// build's wavefront is one lane).
+DSIM_HD inline double wave_sum(double a) {
+#ifndef DSIM_HOST_BUILD
+    for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+#endif
+    return a;
+}
+DSIM_HD inline double wave_max(double a) {
+#ifndef DSIM_HOST_BUILD
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(a, off, 64);
+        a = o > a ? o : a;
+    }
+#endif
+    return a;
+}
+
+// The solve's fallback runs on wavefront 0 alone: its linear algebra is a
+// chain of small dependent steps, and wavefront-level synchronisation keeps
+// each step to a few LDS round trips (team barriers and per-step divisions
+// made it an order of magnitude slower).  Lane r owns rows r, r + wsize, ...
+
+// Natural map of the NCP at L (FP64): sigma = Gd L + gd (into dsig), per
+// contact F_i = L_i - P_K(L_i - rho_i (sigma_i + Gamma(sigma_i))), Gamma the
+// De Saxce term (0, 0, mu |sigma_T|), rho_i = 3 / trace(G_ii) as in the
+// residual check.  With jac, also the blocks of its generalised Jacobian
+//   dF_i/dL = [block i] (I - Pm_i) + C_i G_(i,:),  C_i = rho_i Pm_i D_i,
+// D_i = I + e_N (mu u^T, 0), u = sigma_T / |sigma_T| (0 at no slip): Pm_i in
+// pm, C_i in cm (9 per contact).  Leaves |F|^2, max_i |F_i| and max |L| in
+// dsc[8], dsc[9], dsc[10].  Wavefront 0 only.
 template <class R>
-DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P) {
+DSIM_INLINE DSIM_HD void wave_natural_map(const Team& T, Env<R>& E, const double* L, double* F, bool jac, double* pm,
+                              double* cm) {
     const int k = E.k;
+    for (int r = T.lane; r < k; r += T.wsize) {
+        double s = E.gd[r];
+        const double* g = E.Gd + r * k;
+        for (int c = 0; c < k; ++c) s += g[c] * L[c];
+        E.dsig[r] = s;
+    }
+    T.wave_sync();
+    double a = 0, b = 0, l = 0;
+    for (int c = T.lane; c < E.nc; c += T.wsize) {
+        const double* sg = E.dsig + 3 * c;
+        const double* Lc = L + 3 * c;
+        const double mu = double(E.mu[c]);
+        const double tr = E.Gd[(3 * c) * k + 3 * c] + E.Gd[(3 * c + 1) * k + 3 * c + 1] + E.Gd[(3 * c + 2) * k + 3 * c + 2];
+        const double rho = tr > 0 ? 3.0 / tr : 1.0;
+        const double st = sqrt(sg[0] * sg[0] + sg[1] * sg[1]);
+        const double y[3] = {Lc[0] - rho * sg[0], Lc[1] - rho * sg[1], Lc[2] - rho * (sg[2] + mu * st)};
+        double p[3], Pm[9];
+        cone_proj_jac(y, mu, p, Pm);
+        double n2 = 0;
+        for (int i = 0; i < 3; ++i) {
+            F[3 * c + i] = Lc[i] - p[i];
+            n2 += F[3 * c + i] * F[3 * c + i];
+            l = fabs(Lc[i]) > l ? fabs(Lc[i]) : l;
+        }
+        a += n2;
+        b = sqrt(n2) > b ? sqrt(n2) : b;
+        if (jac) {
+            const double u0 = st > 0 ? sg[0] / st : 0.0, u1 = st > 0 ? sg[1] / st : 0.0;
+            for (int i = 0; i < 3; ++i) {
+                pm[9 * c + 3 * i] = Pm[3 * i];
+                pm[9 * c + 3 * i + 1] = Pm[3 * i + 1];
+                pm[9 * c + 3 * i + 2] = Pm[3 * i + 2];
+                // (Pm D)_(i,:) = Pm_(i,:) + Pm_(i,2) (mu u0, mu u1, 0)
+                cm[9 * c + 3 * i] = rho * (Pm[3 * i] + Pm[3 * i + 2] * mu * u0);
+                cm[9 * c + 3 * i + 1] = rho * (Pm[3 * i + 1] + Pm[3 * i + 2] * mu * u1);
+                cm[9 * c + 3 * i + 2] = rho * Pm[3 * i + 2];
+            }
+        }
+    }
+    a = wave_sum(a);
+    b = wave_max(b);
+    l = wave_max(l);
+    if (T.lane == 0) {
+        E.dsc[8] = a;
+        E.dsc[9] = b;
+        E.dsc[10] = l;
+    }
+    T.wave_sync();
+}
+
+// The natural map for the whole team (wavefront 0 computes; the results are
+// in dsc[8..10] and F for every thread after the call).
+template <class R>
+DSIM_INLINE DSIM_HD void natural_map(const Team& T, Env<R>& E, const double* L, double* F, bool jac, double* pm, double* cm) {
+    if (T.wave == 0) wave_natural_map(T, E, L, F, jac, pm, cm);
+    T.sync();
+}
+
+// In-place Cholesky factor of the SPD k x k matrix M (row-major, lower
+// triangle read): the strictly lower triangle gets L, dinv the reciprocals
+// of L's diagonal.  Right-looking, the column scaling and the trailing
+// update spread over the team (independent chains side by side; on one
+// wavefront each lane's chain of dependent LDS updates was slower).
+// Returns false (to every thread) on a pivot that is not positive.
+DSIM_HD inline bool team_cholesky(const Team& T, double* M, double* dinv, int k) {
+    for (int p = 0; p < k; ++p) {
+        const double d = M[p * k + p];
+        if (!(d > 0.0)) return false;
+        const double inv = 1.0 / sqrt(d);
+        for (int r = p + 1 + T.tid; r < k; r += T.nt) M[r * k + p] *= inv;
+        if (T.tid == 0) dinv[p] = inv;
+        T.sync();
+        const int rem = k - p - 1;
+        for (int idx = T.tid; idx < rem * rem; idx += T.nt) {
+            const int i = p + 1 + idx / rem, j = p + 1 + idx % rem;
+            if (j <= i) M[i * k + j] -= M[i * k + p] * M[j * k + p];
+        }
+        T.sync();
+    }
+    return true;
+}
+
+// Solves (L L^T) x = b with the factor of team_cholesky, x overwriting b.
+// On the GPU lane r keeps x_r in a register and each step broadcasts the
+// finished component with a cross-lane shuffle (k <= 64); the host build
+// runs the same substitution serially.  Wavefront 0 only.
+DSIM_HD inline void wave_cholesky_solve(const Team& T, const double* M, const double* dinv, int k, double* x) {
+#ifdef DSIM_HOST_BUILD
+    for (int i = 0; i < k; ++i) {
+        double s = x[i];
+        for (int j = 0; j < i; ++j) s -= M[i * k + j] * x[j];
+        x[i] = s * dinv[i];
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int j = i + 1; j < k; ++j) s -= M[j * k + i] * x[j];
+        x[i] = s * dinv[i];
+    }
+#else
+    const int r = T.lane;
+    double xr = r < k ? x[r] : 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double xi = __shfl(xr, i, 64) * dinv[i];
+        const double m = r > i && r < k ? M[r * k + i] : 0.0;
+        xr = r == i ? xi : xr - m * xi;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        const double xi = __shfl(xr, i, 64) * dinv[i];
+        const double m = r < i ? M[i * k + r] : 0.0;
+        xr = r == i ? xi : xr - m * xi;
+    }
+    if (r < k) x[r] = xr;
+    T.wave_sync();
+#endif
+}
+
+// Levenberg-Marquardt on the natural map F (a damped semismooth Newton
+// method; Section II.B leaves the solver free), from the impulses in Ld:
+// each iteration solves (H + lam (diag H + eps tr H / k)) d = -J^T F with
+// H = J^T J (J the generalised Jacobian of natural_map, in FP64) and takes
+// d when |F| decreases, else raises the damping.  It needs no mode set and
+// the singular J of redundant contacts does not stop it.  Iterates until
+// max_i |F_i| <= tol max |L|, the iteration cap or a stall (no 10% gain in
+// 6 iterations) within `accept`; returns whether the residual ends within
+// `accept` (near a kink of the natural map, at a contact close to a mode
+// switch, the residual can stall above `tol`).  Uses A (J^T J), A2 (J, then
+// the factor), rhs (F), ytmp (trial F), X (the step), Ld1 (trial), vrow /
+// vcol (per-contact blocks), vdiag (-J^T F), dfr.  The products and the
+// factorisation run on the team, the substitutions and the natural map on
+// wavefront 0 (each phase on the layout measured fastest).
+template <class R>
+DSIM_HD bool lm_solve(const Team& T, Env<R>& E, double tol, double accept, int max_it) {
+    const int k = E.k;
+    double* H = E.A;
+    double* Jm = E.A2;
+    double* F = E.rhs;
+    double* Ft = E.ytmp;
+    double* d = E.X;
+    double* Lt = E.Ld1;
+    double* pm = E.vrow;
+    double* cm = E.vcol;
+    double damp = 1e-3, best = 1e300;
+    int solves = 0, since = 0;
+    bool stop = false;
+    for (int it = 0; it < max_it && !stop; ++it) {
+        natural_map(T, E, E.Ld, F, true, pm, cm);
+        const double f2 = E.dsc[8], fmax = E.dsc[9], lmax = E.dsc[10];
+        if (fmax <= tol * lmax) return true;
+        if (!(f2 == f2)) return false;
+        // a stall (no 10% gain in 6 iterations) within `accept` ends it
+        const double rel = fmax / lmax;
+        since = rel < 0.9 * best ? 0 : since + 1;
+        best = rel < 0.9 * best ? rel : best;
+        if (since >= 6 && rel <= accept) break;
+        for (int idx = T.tid; idx < k * k; idx += T.nt) {
+            const int r = idx / k, j = idx - r * k;
+            const int c = r / 3, a = r - 3 * c;
+            const double* C = cm + 9 * c + 3 * a;
+            double v = C[0] * E.Gd[(3 * c) * k + j] + C[1] * E.Gd[(3 * c + 1) * k + j] + C[2] * E.Gd[(3 * c + 2) * k + j];
+            const int jb = j - 3 * c;
+            if (jb >= 0 && jb < 3) v += (jb == a ? 1.0 : 0.0) - pm[9 * c + 3 * a + jb];
+            Jm[idx] = v;
+        }
+        T.sync();
+        for (int idx = T.tid; idx < k * k; idx += T.nt) {
+            const int i = idx / k, j = idx - i * k;
+            if (j > i) continue;
+            double s = 0;
+            for (int r = 0; r < k; ++r) s += Jm[r * k + i] * Jm[r * k + j];
+            H[i * k + j] = s;
+        }
+        for (int i = T.tid; i < k; i += T.nt) {
+            double g = 0;
+            for (int r = 0; r < k; ++r) g -= Jm[r * k + i] * F[r];
+            E.vdiag[i] = g;  // -J^T F, kept for the retries
+        }
+        T.sync();
+        double tr = 0;
+        for (int i = 0; i < k; ++i) tr += H[i * k + i];
+        bool accepted = false;
+        while (!accepted) {
+            if (damp > 1e12 || ++solves > 4 * max_it) {
+                stop = true;  // the final evaluation at Ld decides
+                break;
+            }
+            const double floor = 1e-12 * tr / k;
+            for (int idx = T.tid; idx < k * k; idx += T.nt) {
+                const int i = idx / k, j = idx - i * k;
+                if (j <= i) Jm[idx] = H[idx] + (i == j ? damp * (H[idx] + floor) : 0.0);
+            }
+            for (int i = T.tid; i < k; i += T.nt) d[i] = E.vdiag[i];
+            T.sync();
+            if (!team_cholesky(T, Jm, E.dfr, k)) {
+                damp *= 4;
+                continue;
+            }
+            if (T.wave == 0) wave_cholesky_solve(T, Jm, E.dfr, k, d);
+            T.sync();
+            for (int r = T.tid; r < k; r += T.nt) Lt[r] = E.Ld[r] + d[r];
+            T.sync();
+            natural_map(T, E, Lt, Ft, false, pm, cm);
+            if (E.dsc[8] < f2) {
+                for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = Lt[r];
+                T.sync();
+                damp = damp / 3 > 1e-12 ? damp / 3 : 1e-12;
+                accepted = true;
+            } else {
+                damp *= 4;
+            }
+        }
+    }
+    // sigma (dsig) and the residual at Ld, whatever ended the loop
+    natural_map(T, E, E.Ld, F, false, pm, cm);
+    return E.dsc[9] <= accept * E.dsc[10];
+}
+
+// ADMM (Section II.B lists it among the NCP solvers) on the De Saxce form
+// of the NCP, from Ld = 0: with s = Gamma(sigma) held at its latest value,
+// the NCP is the optimality condition of the convex cone program
+//   min 1/2 L^T G L + (g + s)^T L  subject to  L in K_mu (each contact),
+// split as L = z: L = (G + rho I)^-1 (rho (z - u) - g - s), z = P_K(L + u),
+// u += L - z, then s from sigma = G z + g.  rho = trace(G) / k.  Every
+// `check` iterations the natural map at z is evaluated; ends with Ld = z at
+// max_i |F_i| <= tol max |z| or after max_it iterations (returns whether it
+// converged).  Uses A ((G + rho I)^-1), A2 (its factor), Ld1 (L), rhs (u),
+// ytmp (s), X, vrow / vcol (scratch of the natural map), dfr.
+template <class R>
+DSIM_HD bool admm_solve(const Team& T, Env<R>& E, double tol, int max_it, int check) {
+    const int k = E.k, nc = E.nc;
+    double* Minv = E.A;
+    double* Fm = E.A2;
+    double* z = E.Ld;
+    double* L = E.Ld1;
+    double* u = E.rhs;
+    double* sv = E.ytmp;
+    double tr = 0;
+    for (int i = 0; i < k; ++i) tr += E.Gd[i * k + i];
+    const double rho = tr > 0 ? tr / k : 1.0;
+    for (int idx = T.tid; idx < k * k; idx += T.nt) {
+        const int i = idx / k, j = idx - i * k;
+        Fm[idx] = E.Gd[idx] + (i == j ? rho : 0.0);
+    }
+    for (int r = T.tid; r < k; r += T.nt) {
+        z[r] = 0;
+        u[r] = 0;
+        sv[r] = 0;
+    }
+    T.sync();
+    if (!team_cholesky(T, Fm, E.dfr, k)) return false;
+    // explicit inverse, one column per thread (forward and back substitution)
+    for (int col = T.tid; col < k; col += T.nt) {
+        for (int i = 0; i < k; ++i) {
+            double x = (i == col) ? 1.0 : 0.0;
+            for (int j = 0; j < i; ++j) x -= Fm[i * k + j] * Minv[j * k + col];
+            Minv[i * k + col] = x * E.dfr[i];
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double x = Minv[i * k + col];
+            for (int j = i + 1; j < k; ++j) x -= Fm[j * k + i] * Minv[j * k + col];
+            Minv[i * k + col] = x * E.dfr[i];
+        }
+    }
+    T.sync();
+    for (int it = 0; it < max_it; ++it) {
+        // L = Minv (rho (z - u) - g - s)
+        for (int r = T.tid; r < k; r += T.nt) E.X[r] = rho * (z[r] - u[r]) - E.gd[r] - sv[r];
+        T.sync();
+        for (int r = T.tid; r < k; r += T.nt) {
+            double a = 0;
+            for (int c = 0; c < k; ++c) a += Minv[r * k + c] * E.X[c];
+            L[r] = a;
+        }
+        T.sync();
+        // z = P_K(L + u), u += L - z (per contact)
+        for (int c = T.tid; c < nc; c += T.nt) {
+            const double y[3] = {L[3 * c] + u[3 * c], L[3 * c + 1] + u[3 * c + 1], L[3 * c + 2] + u[3 * c + 2]};
+            double p[3], Pm[9];
+            cone_proj_jac(y, double(E.mu[c]), p, Pm);
+            for (int a = 0; a < 3; ++a) {
+                z[3 * c + a] = p[a];
+                u[3 * c + a] += L[3 * c + a] - p[a];
+            }
+        }
+        T.sync();
+        if ((it + 1) % check == 0) {
+            natural_map(T, E, z, E.X, false, E.vrow, E.vcol);
+            if (E.dsc[9] <= tol * E.dsc[10]) return true;
+            if (!(E.dsc[8] == E.dsc[8])) return false;
+        } else {
+            // sigma at z for the De Saxce term
+            for (int r = T.tid; r < k; r += T.nt) {
+                double a = E.gd[r];
+                for (int c = 0; c < k; ++c) a += E.Gd[r * k + c] * z[c];
+                E.dsig[r] = a;
+            }
+            T.sync();
+        }
+        for (int c = T.tid; c < nc; c += T.nt) {
+            const double* sg = E.dsig + 3 * c;
+            sv[3 * c] = 0;
+            sv[3 * c + 1] = 0;
+            sv[3 * c + 2] = double(E.mu[c]) * sqrt(sg[0] * sg[0] + sg[1] * sg[1]);
+        }
+        T.sync();
+    }
+    return false;
+}
+
+// Modes of the impulses in Ld (reading R5 of the mode split, with the
+// thresholds of mode_eps): breaking if the normal impulse is at most
+// eps s_Lam, else sticking if the slip is at most eps s_sig, else sliding.
+template <class R>
+DSIM_HD void classify_modes(const Team& T, Env<R>& E, const Params& P) {
+    // sigma at Ld is in dsig (the last natural_map); scales as the residual check
+    if (T.tid == 0) {
+        double smax, lmax;
+        scales(E, P, smax, lmax);
+        double sl = 1e-300;
+        for (int c = 0; c < E.nc; ++c) sl = E.Ld[3 * c + 2] > sl ? E.Ld[3 * c + 2] : sl;
+        for (int c = 0; c < E.nc; ++c) {
+            const double* s = E.dsig + 3 * c;
+            const double st = sqrt(s[0] * s[0] + s[1] * s[1]);
+            int md = SLD;
+            if (E.Ld[3 * c + 2] <= P.mode_eps * sl)
+                md = BRK;
+            else if (st <= P.mode_eps * smax)
+                md = STK;
+            E.cmode[c] = md;
+        }
+    }
+    T.sync();
+}
+
+// The fallback pass of the solve, for an environment the first pass left
+// unsolved, from that pass's impulses (in Ld): damped Newton on the natural
+// map; if that does not converge, ADMM from zero impulses and damped Newton
+// from its result.  A solution within the tolerance takes the modes its
+// refinement confirms, or else (a contact at a mode boundary) the modes of
+// the classification.  Returns whether it found one.
+template <class R>
+DSIM_HD bool fallback_solve(const Team& T, Env<R>& E, const Params& P) {
+    // FP64 iterations: both forms converge them well below the FP32 form's
+    // tolerance, so that its solution is as accurate as a refined one
+    const double tol = 0.25 * (P.ncp_tol < 1e-11 ? P.ncp_tol : 1e-11);
+    const double accept = 0.25 * P.ncp_tol;
+    bool found = lm_solve(T, E, tol, accept, kLmIters);
+    if (!found) {
+        admm_solve(T, E, 1e-7, kAdmmIters, 20);
+        found = lm_solve(T, E, tol, accept, kLmIters);
+    }
+    if (!found) return false;
+    const int k = E.k;
+    for (int r = T.tid; r < k; r += T.nt) E.vdiag[r] = E.Ld[r];
+    classify_modes(T, E, P);
+    bool ok = polish(T, E, P);
+    if (ok) {
+        // the refinement solves the mode equations; its result is kept only
+        // if it also meets the natural-map tolerance
+        natural_map(T, E, E.Ld, E.rhs, false, E.vrow, E.vcol);
+        ok = E.dsc[9] <= accept * E.dsc[10];
+    }
+    if (!ok) {
+        for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = E.vdiag[r];
+        T.sync();
+        fp64_sigma(T, E);
+        classify_modes(T, E, P);
+    }
+    return true;
+}
+
+// The NCP.  First pass (P.pass == 0): sweeps in working precision and
+// refinement in FP64, repeated in rounds until the refinement reaches a
+// consistent solution that meets the natural-map tolerance.  Fallback pass
+// (P.pass == 1, run only for the environments the first pass left
+// unsolved): fallback_solve from the first pass's impulses `lam_start` (its
+// output).  Then the paper's reduced system at the solution, factorised for
+// the derivative.
+template <class R>
+DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P, const R* lam_start) {
+    const int k = E.k;
+    bool ok = false;
+    if (P.pass == 1 && k > 0) {
+        for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = double(lam_start[3 * E.c0 + r]);
+        T.sync();
+        ok = fallback_solve(T, E, P);
+        if (!ok) {
+            // keep the first pass's impulses, with the modes they classify to
+            for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = double(lam_start[3 * E.c0 + r]);
+            T.sync();
+            fp64_sigma(T, E);
+            classify_modes(T, E, P);
+        }
+    }
     for (int r = T.tid; r < k; r += T.nt) {
         E.Lam[r] = 0;
         E.sig[r] = E.g[r];
     }
     for (int c = T.tid; c < E.nc; c += T.nt) E.lmode[c] = BRK;
     T.sync();
-    bool ok = false;
-    for (int round = 0; round < P.ncp_rounds && k > 0; ++round) {
+    for (int round = 0; P.pass == 0 && round < P.ncp_rounds && k > 0; ++round) {
         nsgs(T, E, P.ncp_sweeps);
         if (round > 0) {
             // A round whose sweeps end in the state (impulses, sigma, modes)
@@ -794,10 +1261,18 @@ DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P) {
         }
         T.sync();
         ok = polish(T, E, P);
+        if (ok) {
+            // the refinement solves the equations of its mode set; the
+            // solution is taken when it also meets the natural-map
+            // tolerance, the test of the final residual check
+            natural_map(T, E, E.Ld, E.rhs, false, E.vrow, E.vcol);
+            ok = E.dsc[9] <= P.ncp_tol * E.dsc[10];
+        }
         if (ok) break;
     }
-    if (!ok && k > 0) {
-        // keep the Gauss-Seidel iterate and its modes
+    if (P.pass == 0 && !ok && k > 0) {
+        // keep the Gauss-Seidel iterate and its modes (the fallback pass
+        // starts from these impulses)
         for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = double(E.Lam[r]);
         for (int c = T.tid; c < E.nc; c += T.nt) E.cmode[c] = E.lmode[c];
         T.sync();

@@ -15,7 +15,7 @@ namespace dsim {
 // is reused.
 template <class R>
 DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
-                          const Handover* H, char* rec) {
+                          const Handover* H, char* rec, const R* lam_start) {
     const int nb = E.nb, n = E.nv, k = E.k, nc = E.nc;
     kinematics(T, E, B, q);
     mass_matrix(T, E);
@@ -55,7 +55,7 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
         team_put(T, rec, H->J, E.J, k * n);
         T.sync();
     }
-    solve_ncp(T, E, P);
+    solve_ncp(T, E, P, lam_start);
     // v+ = v_f + M^-1 J^T Lam and a+ = a_f + M^-1 J^T Lam / dt
     for (int i = T.tid; i < n; i += T.nt) {
         double s = 0;
@@ -473,9 +473,9 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
         T.sync();
         for (int idx = T.tid; idx < n * k; idx += T.nt) {
             const int i = idx / k, rho = idx - i * k;
-            R s = 0;
-            for (int c = 0; c < k; ++c) s += E.KT[c * n + i] * CZ[c * k + rho];
-            E.T[idx] = -s;
+            double s = 0;
+            for (int c = 0; c < k; ++c) s += double(E.KT[c * n + i]) * double(CZ[c * k + rho]);
+            E.T[idx] = R(-s);
         }
     } else {
         for (int idx = T.tid; idx < n * k; idx += T.nt) E.T[idx] = 0;
@@ -483,9 +483,9 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
     T.sync();
     for (int idx = T.tid; idx < n * n; idx += T.nt) {
         const int i = idx / n, j = idx - i * n;
-        R s = (i == j) ? R(1) : R(0);
-        for (int r = 0; r < k; ++r) s += E.T[i * k + r] * E.J[r * n + j];
-        E.P[idx] = s;
+        double s = (i == j) ? 1.0 : 0.0;
+        for (int r = 0; r < k; ++r) s += double(E.T[i * k + r]) * double(E.J[r * n + j]);
+        E.P[idx] = R(s);
     }
     T.sync();
     // Q = P M^-1 with the FP64 M^-1 of the step
@@ -500,21 +500,24 @@ DSIM_HD void jacobian(const Team& T, Env<R>& E, const BatchView<R>& B, const Par
     const int off = B.jac_off[E.e];
     for (int idx = T.tid; idx < n * n; idx += T.nt) {
         const int i = idx / n, j = idx - i * n;
-        R sq = 0, sv = 0, se = 0;
+        // FP64 sums of the working-precision operands: on gfx950 an FP64
+        // FMA issues at the rate of an unpacked FP32 one, and the sums of
+        // the assembly cancel
+        double sq = 0, sv = 0, se = 0;
         for (int l = 0; l < n; ++l) {
-            const R ql = E.Q[i * n + l];
-            sq += ql * E.dTq[l * n + j];
-            sv += ql * E.dTv[l * n + j];
+            const double ql = double(E.Q[i * n + l]);
+            sq += ql * double(E.dTq[l * n + j]);
+            sv += ql * double(E.dTv[l * n + j]);
         }
-        for (int r = 0; r < k; ++r) se += E.T[i * k + r] * E.E[r * n + j];
+        for (int r = 0; r < k; ++r) se += double(E.T[i * k + r]) * double(E.E[r * n + j]);
         // Baumgarte damping: the normal rows of the contact equation also
         // depend on v through -kd J_N v (Appendix D)
-        R sd = 0;
+        double sd = 0;
         if (P.gap_mode == 1 && P.kd != 0.0)
-            for (int r = 2; r < k; r += 3) sd += E.T[i * k + r] * E.J[r * n + j];
-        dvdq[off + idx] = -dt * sq + se;
-        dvdv[off + idx] = E.P[idx] - dt * sv - R(P.kd) * sd;
-        dvdtau[off + idx] = dt * E.Q[idx];
+            for (int r = 2; r < k; r += 3) sd += double(E.T[i * k + r]) * double(E.J[r * n + j]);
+        dvdq[off + idx] = R(-P.dt * sq + se);
+        dvdv[off + idx] = R(double(E.P[idx]) - P.dt * sv - P.kd * sd);
+        dvdtau[off + idx] = R(P.dt * double(E.Q[idx]));
     }
     T.sync();
 }
@@ -914,7 +917,7 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
     const Handover H = handover_layout<R>(D);
     char* rec = ld ? handover_base(ld, B.n_env) + size_t(e) * H.bytes : nullptr;
     if (!entry_has_derivative(entry)) {
-        step_forward(T, E, B, P, q, rec ? &H : nullptr, rec);
+        step_forward(T, E, B, P, q, rec ? &H : nullptr, rec, static_cast<const R*>(lam));
         write_step(T, E, v_next, lam, mode, status);
         if (ld) {
             double* l = ld + size_t(E.e) * kLdStride;

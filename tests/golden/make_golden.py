@@ -5,9 +5,11 @@ nothing here comes from the HIP path.
     python tests/golden/make_golden.py [name ...]
 
 Each file holds, per listed environment: index, v+ (n_v), J^T Lam (n_v),
-modes (n_c), margin, solver ok flag, uniqueness of the v+ derivative, and the
-full Jacobian d v+ / d(dq, v, tau) (n_v x 3 n_v), and the NCP data (G, g,
-mu) so that a different but valid GPU solution can be recognised.  The
+modes (n_c), margin, solver ok flag, whether the solver needed its fallback,
+uniqueness of the v+ derivative, the full Jacobian d v+ / d(dq, v, tau)
+(n_v x 3 n_v), the contact Jacobian J (3 n_c x n_v, to form J^T Lam of a
+GPU impulse) and the NCP data (G, g, mu) so that a different but valid GPU
+solution can be recognised.  The
 parameter sets hold the derivatives of v+ in the body masses and friction
 coefficients (n_v x (n_b + n_c)) instead of the Jacobian.
 """
@@ -25,21 +27,36 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from paper_2409_07107_amd import scenes  # noqa: E402
 from oracle import derivative, rollout, step  # noqa: E402
 
+def spread(n_env, count, seed):
+    """`count` environment indices of an n_env batch: the first and last four
+    (the batch's edges) and the rest drawn uniformly without replacement from
+    the interior (a seeded draw: the same list every time)."""
+    rng = np.random.default_rng(seed)
+    mid = np.sort(rng.choice(np.arange(4, n_env - 4), size=count - 8, replace=False))
+    return [0, 1, 2, 3] + [int(x) for x in mid] + list(range(n_env - 4, n_env))
+
+
 # name -> (workload, n_env of the batch, seed, env indices to store)
 SETS = {
     "cube8": ("cube", 8, 1, list(range(8))),
     "arm7_64": ("arm7", 64, 2, list(range(64))),
     "tree36_24": ("tree36", 24, 3, list(range(24))),
-    # full-size batches: sampled environments (first, interior, ragged tail)
-    "arm7_4096_sample": ("arm7", 4096, 0, [0, 1, 2, 63, 64, 1000, 2047, 2048, 3001, 4093, 4094, 4095]),
-    "tree36_16384_sample": ("tree36", 16384, 0, [0, 1, 2, 3, 255, 256, 4097, 8191, 8192, 12000,
-                                                   16379, 16380, 16381, 16382, 16383]),
+    # full-size batches: sampled environments spread over the whole batch
+    "arm7_4096_sample": ("arm7", 4096, 0, spread(4096, 64, 100)),
+    "tree36_16384_sample": ("tree36", 16384, 0, spread(16384, 64, 101)),
     # sphere contacts: free balls and arms with capsule ends (gap mode 0)
     "spheres_64": ("spheres", 64, 41, list(range(32))),
-    "spheres_16384_sample": ("spheres", 16384, 0, [0, 1, 2, 3, 4097, 8190, 8191, 16382, 16383]),
+    "spheres_16384_sample": ("spheres", 16384, 0, spread(16384, 32, 102)),
     # ragged trees of 7..40 dof with 0..16 contacts
-    "mixed_8192_sample": ("mixed", 8192, 0, [0, 1, 2, 3, 4, 5, 6, 7, 1000, 2047, 2048, 4095, 4096, 6000,
-                                             8188, 8189, 8190, 8191]),
+    "mixed_8192_sample": ("mixed", 8192, 0, spread(8192, 48, 103)),
+}
+
+# hard contact problems: the first `count` environments of the full tree36
+# batch whose NCP the oracle's sweeps, mode Newton and active-set search do
+# not finish (its damped-Newton / ADMM fallback does); chosen by the oracle
+# alone.  name -> (workload, n_env, seed, count, scan limit)
+HARD = {
+    "tree36_hard": ("tree36", 16384, 0, 24, 2000),
 }
 
 # rollouts: name -> (workload, n_env, seed, steps, gap_mode, generator options)
@@ -107,27 +124,41 @@ def _one(e):
     r = step.forward(env)
     d = derivative.ift(env, r)
     return dict(env=e, vnext=r["vnext"], JtLam=r["JtLam"], modes=np.array(r["modes"], dtype=np.int8),
-                G=r["G"], g=r["g"], mu=r["model"].mu,
+                G=r["G"], g=r["g"], mu=r["model"].mu, J=r["J"],
                 margin=r["margin"], ok=bool(r["info"]["ok"]), unique=bool(d["unique_v"]), jac=d["jac"],
-                residual=float(r["residual"].max()) if len(r["residual"]) else 0.0)
+                residual=float(r["residual"].max()) if len(r["residual"]) else 0.0,
+                fallback=bool(r["info"].get("fallback", False)))
+
+
+def _needs_fallback(e):
+    r = step.forward(_BATCH.env(e))
+    return e, bool(r["info"].get("fallback", False))
 
 
 def make(name):
     global _BATCH
-    wl, n, seed, envs = SETS[name]
-    _BATCH = scenes.make(wl, n, seed=seed)
+    if name in HARD:
+        wl, n, seed, count, limit = HARD[name]
+        _BATCH = scenes.make(wl, n, seed=seed)
+        with Pool(8) as p:
+            flags = p.map(_needs_fallback, range(limit))
+        envs = [e for e, f in flags if f][:count]
+        print(name, "scanned", limit, "environments, fallback needed by", sum(f for _, f in flags), flush=True)
+    else:
+        wl, n, seed, envs = SETS[name]
+        _BATCH = scenes.make(wl, n, seed=seed)
     with Pool(min(8, len(envs))) as p:
         res = p.map(_one, envs)
     out = dict(envs=np.array(envs), workload=wl, n_env=n, seed=seed)
     ragged = len({r["jac"].shape for r in res}) > 1 or len({r["G"].shape for r in res}) > 1
     out["ragged"] = ragged
-    for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu"):
+    for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu", "J"):
         if ragged:  # one array per environment (no object arrays in the files)
             for i, r in enumerate(res):
                 out[f"{key}__{i}"] = np.asarray(r[key])
         else:
             out[key] = np.array([r[key] for r in res])
-    for key in ("margin", "ok", "unique", "residual"):
+    for key in ("margin", "ok", "unique", "residual", "fallback"):
         out[key] = np.array([r[key] for r in res])
     path = os.path.join(HERE, f"{name}.npz")
     np.savez_compressed(path, **out)
@@ -169,7 +200,7 @@ def make_rollout(name):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(SETS) + list(ROLLOUTS) + list(PARAMS)):
+    for name in (sys.argv[1:] or list(SETS) + list(HARD) + list(ROLLOUTS) + list(PARAMS)):
         if name in ROLLOUTS:
             make_rollout(name)
         elif name in PARAMS:

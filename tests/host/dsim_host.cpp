@@ -5,8 +5,8 @@
 // one thread.  This file instantiates that build: every environment of a
 // batch whose arrays are HOST memory is run through run_env exactly as one
 // workgroup of the GPU launch would run it, in the same launch order (the
-// step launch over all environments, then the derivative launch for the
-// derivative entries).  It is a verification tool (address checking of each
+// two passes of the step launch over all environments, then the derivative
+// launch for the derivative entries).  It is a verification tool (address checking of each
 // scratch region, the solver's behaviour on chosen environments), never a
 // path of the library: the package has no CPU fallback.
 //
@@ -98,9 +98,10 @@ Dims dims_of(const dsim_batch* b) {
 template <class R>
 int pass(const dsim_batch* b, const dsim_params* p, int entry, const R* q, const R* v, const R* tau, const R* gbar,
          const R* gbar2, R* v_next, R* lam, int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, R* o4, R* o5,
-         double* ld, int e0, int e1, int region) {
+         double* ld, int e0, int e1, int region, int solve_pass = 0) {
     const BatchView<R> B = view<R>(b);
-    const Params P = params_of(p);
+    Params P = params_of(p);
+    P.pass = solve_pass;
     const Dims D = dims_of(b);
     Env<R> E;
     const size_t bytes = carve<R>(nullptr, D, entry, E);
@@ -119,6 +120,7 @@ int pass(const dsim_batch* b, const dsim_params* p, int entry, const R* q, const
             status[e] = ST_SIZE;
             continue;
         }
+        if (solve_pass == 1 && !(status[e] & (ST_NCP | ST_POLISH))) continue;
         if (region) {
             host_region_alloc = region_alloc;
             carve<R>(reinterpret_cast<char*>(16), D, entry, E);
@@ -141,11 +143,15 @@ int run(const dsim_batch* b, const dsim_params* p, int entry, const void* q, con
     auto c = [](const void* x) { return static_cast<const R*>(x); };
     auto w = [](void* x) { return static_cast<R*>(x); };
     double* ld = static_cast<double*>(ws);
-    if (!entry_has_derivative(entry))
-        return pass<R>(b, p, entry, c(q), c(v), c(tau), c(gbar), c(gbar2), w(v_next), w(lam), mode, status, w(o1),
-                       w(o2), w(o3), w(o4), w(o5), ld, e0, e1, region);
-    pass<R>(b, p, ENTRY_STEP, c(q), c(v), c(tau), nullptr, nullptr, w(v_next), w(lam), mode, status, nullptr, nullptr,
-            nullptr, nullptr, nullptr, ld, e0, e1, region);
+    if (!entry_has_derivative(entry)) {
+        for (int sp = 0; sp < 2; ++sp)
+            pass<R>(b, p, entry, c(q), c(v), c(tau), c(gbar), c(gbar2), w(v_next), w(lam), mode, status, w(o1),
+                    w(o2), w(o3), w(o4), w(o5), ld, e0, e1, region, sp);
+        return 0;
+    }
+    for (int sp = 0; sp < 2; ++sp)
+        pass<R>(b, p, ENTRY_STEP, c(q), c(v), c(tau), nullptr, nullptr, w(v_next), w(lam), mode, status, nullptr,
+                nullptr, nullptr, nullptr, nullptr, ld, e0, e1, region, sp);
     return pass<R>(b, p, entry, c(q), c(v), c(tau), c(gbar), c(gbar2), w(v_next), w(lam), mode, status, w(o1), w(o2),
                    w(o3), w(o4), w(o5), ld, e0, e1, region);
 }

@@ -1,12 +1,34 @@
 """Shared helpers of the GPU parity tests: load the oracle's stored results,
 run the HIP path on the same seeded batch, compare per environment.
 
-Error statistic (per environment, per block dq / dv / dtau of the Jacobian):
-|J_gpu - J_oracle|_F / max(|J_oracle|_F, 1e-8); v+ is compared in the max norm
-relative to max(|v+|_inf, |v|_inf, |g| dt).  Environments enter the statistic
-when the oracle solved the NCP, its v+ derivative is unique, its mode margin is
-at least `margin_min` and the GPU reports no solver failure; the others are
-counted and reported.
+Per environment the comparison covers:
+  * v+ in the max norm relative to max(|v+|_inf, |v|_inf, |g| dt);
+  * J^T Lam (unique even when redundant contacts make Lam non-unique), with
+    the GPU impulses mapped through the oracle's contact Jacobian, in the
+    max norm relative to max(|J^T Lam|_inf, s), s the impulse that stops the
+    free motion mapped through J^T (the scale when every contact separates);
+  * each block dq / dv / dtau of the Jacobian: |J_gpu - J_oracle|_F /
+    max(|J_oracle|_F, 1e-8) within the tolerance, and element by element
+    max |dJ_ij| / max |J_oracle| over the block within twice it (a wrong
+    small entry cannot hide in a large block; an entry's own rounding is not
+    averaged out, hence the factor);
+  * the contact modes, exactly.
+
+Categories (every environment falls in one; all are counted and printed):
+  gated     the oracle solved the NCP, its v+ derivative is unique, its mode
+            margin is at least `margin`, the GPU reports no solver failure
+            and found the oracle's modes: every error within the tolerance;
+  near      as gated, but with a margin between `floor` and `margin`: near
+            a mode switch the derivative's sensitivity to rounding grows like
+            u / margin (u the unit roundoff of the form), so the tolerance is
+            tol + C u / margin;
+  unpinned  margin below `floor` or a non-unique v+ derivative (a contact at
+            a switching surface: several one-sided derivatives are correct);
+  alt       the GPU's modes or v+ differ from the oracle's: its impulses must
+            satisfy every NCP condition for the oracle's (G, g, mu)
+            (`ncp.check`, pinned to reject each violated condition);
+  flagged   the GPU solver reports failure (counted against a share);
+  oracle    the oracle's solver did not finish.
 """
 from __future__ import annotations
 
@@ -18,12 +40,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
-# FP64: 1e-10; FP32 form: 1e-4.  Near a mode switch (stick-slip, lift-off)
-# the derivative's sensitivity to rounding grows like eps / margin, so
-# environments with a mode margin below `margin` are reported, not gated
-# (1e-6 for FP64, 1e-2 for the FP32 form).
-TOL = {0: dict(v=1e-10, jac=1e-10, margin=1e-6, ncp=1e-8),
-       1: dict(v=1e-4, jac=1e-4, margin=1e-2, ncp=1e-4)}
+# FP64 form: 1e-10; FP32 form: 1e-4.  `u` is the unit roundoff of the form's
+# working precision, `C` the constant of the near-switch tolerance (measured:
+# see the design doc, the error-versus-margin figures of the parity runs).
+TOL = {0: dict(v=1e-10, jac=1e-10, jtl=1e-10, margin=1e-6, floor=1e-11, u=1.1e-16, C=100.0, ncp=1e-8),
+       1: dict(v=1e-4, jac=1e-4, jtl=1e-4, margin=1e-3, floor=1e-6, u=6.0e-8, C=100.0, ncp=1e-4)}
+
+
+def scaled(tol, key, margin):
+    """The tolerance of quantity `key` for an environment at this margin."""
+    if margin >= tol["margin"]:
+        return tol[key]
+    return tol[key] + tol["C"] * tol["u"] / max(margin, 1e-300)
 
 
 def ncp_valid(G, g, mu, lam, tol):
@@ -37,8 +65,9 @@ def load_golden(name):
     d = {k: z[k] for k in z.files}
     if "ragged" in d and bool(d["ragged"]):  # per-environment arrays -> lists
         n = len(d["envs"])
-        for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu"):
-            d[key] = [d.pop(f"{key}__{i}") for i in range(n)]
+        for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu", "J"):
+            if f"{key}__0" in d:
+                d[key] = [d.pop(f"{key}__{i}") for i in range(n)]
     return d
 
 
@@ -47,12 +76,27 @@ def say(*a):
     sys.stdout.flush()
 
 
+def _impulse_scale(G, g, J):
+    """|J^T s|_inf with s_i = rho_i |g_i| (rho_i = 3 / trace(G_ii)) along
+    each contact's axes: the generalised impulse that stops the free motion."""
+    G, g, J = np.asarray(G), np.asarray(g), np.asarray(J)
+    nc = len(g) // 3
+    if nc == 0:
+        return 0.0
+    s = np.zeros(3 * nc)
+    for i in range(nc):
+        tr = np.trace(G[3 * i:3 * i + 3, 3 * i:3 * i + 3])
+        s[3 * i:3 * i + 3] = (3.0 / tr if tr > 0 else 1.0) * np.linalg.norm(g[3 * i:3 * i + 3])
+    return float(np.abs(J.T).max() * s.max())
+
+
 def compare(batch, gold, out, db, precision, envs=None, label=""):
     """Returns a dict of statistics; `out` is the output dict of
-    dsim.step_jacobian on `db` (a DeviceBatch over `batch`)."""
+    dsim.step_jacobian (or step) on `db` (a DeviceBatch over `batch`)."""
     from paper_2409_07107_amd import dsim
     tol = TOL[precision]
     vnext = out["v_next"].double().cpu().numpy()
+    lam_all = out["lam"].double().cpu().numpy()
     modes = out["mode"].cpu().numpy()
     status = out["status"].cpu().numpy()
     rows = []
@@ -64,41 +108,85 @@ def compare(batch, gold, out, db, precision, envs=None, label=""):
         v = batch.v[d0:d1]
         scale_v = max(np.abs(ref_v).max(), np.abs(v).max(), 9.81 * batch.dt)
         ev = np.abs(vnext[d0:d1] - ref_v).max() / scale_v
+        lam = lam_all[3 * c0:3 * c1]
+        ejtl = 0.0
+        if "J" in gold and c1 > c0:
+            Jc = np.asarray(gold["J"][gi])
+            ref = np.asarray(gold["JtLam"][gi])
+            s = max(np.abs(ref).max(), _impulse_scale(gold["G"][gi], gold["g"][gi], Jc), 1e-300)
+            ejtl = np.abs(Jc.T @ lam - ref).max() / s
         J = dsim.split_jacobian(db, out, e) if "dvdq" in out else None
         nv = d1 - d0
-        ej = []
+        ej, ee = [], []
         if J is not None:
             for b in range(3):
                 A = J[:, b * nv:(b + 1) * nv]
                 B = gold["jac"][gi][:, b * nv:(b + 1) * nv]
                 ej.append(np.linalg.norm(A - B) / max(np.linalg.norm(B), 1e-8))
+                ee.append(np.abs(A - B).max() / max(np.abs(B).max(), 1e-8))
         st = int(status[e])
+        margin = float(gold["margin"][gi])
         mode_ok = bool(np.array_equal(modes[c0:c1].astype(np.int8), gold["modes"][gi].astype(np.int8)))
         solver_ok = not (st & (dsim.ST_NCP_NOT_CONVERGED | dsim.ST_POLISH_FAILED))
-        # several NCP solutions: a GPU solution that differs from the oracle's
-        # must satisfy every NCP condition for the oracle's own (G, g, mu)
-        alt = alt_valid = False
-        if solver_ok and gold["ok"][gi] and (not mode_ok or ev > tol["v"]):
-            alt = True
-            lam = out["lam"][3 * c0:3 * c1].double().cpu().numpy()
+        oracle_ok = bool(gold["ok"][gi])
+        unique = bool(gold["unique"][gi])
+        alt_valid = False
+        if not oracle_ok:
+            cat = "oracle"
+        elif not solver_ok:
+            cat = "flagged"
+        elif not mode_ok or ev > scaled(tol, "v", margin):
+            # several NCP solutions: a GPU solution that differs from the
+            # oracle's must satisfy every NCP condition for the oracle's data
+            cat = "alt"
             alt_valid = ncp_valid(gold["G"][gi], gold["g"][gi], gold["mu"][gi], lam, tol["ncp"])
-        included = bool(gold["ok"][gi] and gold["unique"][gi] and gold["margin"][gi] >= tol["margin"]
-                        and solver_ok and not alt)
-        rows.append(dict(env=e, ev=ev, ej=ej, status=st, mode_ok=mode_ok, included=included,
-                         margin=float(gold["margin"][gi]), alt=alt, alt_valid=alt_valid))
-    inc = [r for r in rows if r["included"]]
-    stats = dict(n=len(rows), included=len(inc),
-                 v_max=max((r["ev"] for r in inc), default=0.0),
-                 jac_max=max((max(r["ej"]) for r in inc if r["ej"]), default=0.0),
-                 jac_median=float(np.median([max(r["ej"]) for r in inc if r["ej"]])) if inc and inc[0]["ej"] else 0.0,
-                 modes_agree=sum(r["mode_ok"] for r in inc),
-                 solver_flags=sum(1 for r in rows if r["status"] & (dsim.ST_NCP_NOT_CONVERGED | dsim.ST_POLISH_FAILED)),
-                 alternatives=sum(r["alt"] for r in rows),
-                 alternatives_invalid=sum(r["alt"] and not r["alt_valid"] for r in rows),
-                 rows=rows)
-    say(f"[{label}] envs {stats['n']} included {stats['included']} v+ max {stats['v_max']:.2e} "
-        f"jac max {stats['jac_max']:.2e} median {stats['jac_median']:.2e} modes agree "
-        f"{stats['modes_agree']}/{stats['included']} solver flags {stats['solver_flags']} "
-        f"other valid NCP solutions {stats['alternatives'] - stats['alternatives_invalid']} "
-        f"invalid {stats['alternatives_invalid']}")
+        elif not unique or margin < tol["floor"]:
+            cat = "unpinned"
+        elif margin < tol["margin"]:
+            cat = "near"
+        else:
+            cat = "gated"
+        lim = scaled(tol, "jac", margin)
+        ok = (ev <= scaled(tol, "v", margin) and ejtl <= scaled(tol, "jtl", margin)
+              and (not ej or (max(ej) <= lim and max(ee) <= 2 * lim)))
+        rows.append(dict(env=e, ev=ev, ej=ej, ee=ee, ejtl=ejtl, status=st, mode_ok=mode_ok, cat=cat,
+                         margin=margin, ok=ok, alt_valid=alt_valid,
+                         fallback=bool(gold["fallback"][gi]) if "fallback" in gold else False))
+    by = {c: [r for r in rows if r["cat"] == c] for c in ("gated", "near", "unpinned", "alt", "flagged", "oracle")}
+    inc = by["gated"] + by["near"]
+    stats = dict(n=len(rows), gated=len(by["gated"]), near=len(by["near"]), included=len(inc),
+                 unpinned=len(by["unpinned"]), alternatives=len(by["alt"]),
+                 alternatives_invalid=sum(not r["alt_valid"] for r in by["alt"]),
+                 solver_flags=len(by["flagged"]), oracle_failed=len(by["oracle"]),
+                 failures=[r for r in inc if not r["ok"]],
+                 v_max=max((r["ev"] for r in by["gated"]), default=0.0),
+                 jtl_max=max((r["ejtl"] for r in by["gated"]), default=0.0),
+                 jac_max=max((max(r["ej"]) for r in by["gated"] if r["ej"]), default=0.0),
+                 elem_max=max((max(r["ee"]) for r in by["gated"] if r["ee"]), default=0.0),
+                 jac_median=float(np.median([max(r["ej"]) for r in by["gated"] if r["ej"]]))
+                 if any(r["ej"] for r in by["gated"]) else 0.0,
+                 modes_agree=sum(r["mode_ok"] for r in inc), rows=rows)
+    say(f"[{label}] envs {stats['n']} gated {stats['gated']} near-switch {stats['near']} unpinned "
+        f"{stats['unpinned']} other valid NCP solutions {stats['alternatives'] - stats['alternatives_invalid']} "
+        f"(invalid {stats['alternatives_invalid']}) solver flags {stats['solver_flags']} oracle failed "
+        f"{stats['oracle_failed']} | gated: v+ max {stats['v_max']:.2e} J^T Lam max {stats['jtl_max']:.2e} "
+        f"jac max {stats['jac_max']:.2e} (elementwise {stats['elem_max']:.2e}) median {stats['jac_median']:.2e} "
+        f"| failures {len(stats['failures'])}")
+    for r in by["near"] + by["unpinned"] + by["alt"]:
+        say(f"    env {r['env']} {r['cat']} margin {r['margin']:.1e} v+ {r['ev']:.1e} J^T Lam {r['ejtl']:.1e} "
+            f"jac {max(r['ej']) if r['ej'] else 0:.1e} elementwise {max(r['ee']) if r['ee'] else 0:.1e} "
+            f"modes agree {r['mode_ok']} status {r['status']}")
+    for r in stats["failures"]:
+        say(f"    FAIL env {r['env']} {r['cat']} margin {r['margin']:.1e} v+ {r['ev']:.1e} J^T Lam {r['ejtl']:.1e} "
+            f"jac {max(r['ej']) if r['ej'] else 0:.1e} elementwise {max(r['ee']) if r['ee'] else 0:.1e}")
     return stats
+
+
+def assert_parity(st, min_included, max_flagged=None):
+    """The gate every parity test applies to compare()'s statistics."""
+    assert st["included"] >= min_included, "too few comparable environments"
+    assert not st["failures"], f"{len(st['failures'])} environments outside tolerance"
+    assert st["modes_agree"] == st["included"]
+    assert st["alternatives_invalid"] == 0
+    if max_flagged is not None:
+        assert st["solver_flags"] <= max_flagged

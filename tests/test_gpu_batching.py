@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07107_amd import scenes
-from tests.parity_util import TOL, compare, load_golden, say
+from tests.parity_util import TOL, assert_parity, compare, load_golden, say
 
 pytestmark = pytest.mark.gpu
 
@@ -40,16 +40,11 @@ def test_mixed_full_size_parity_planned_and_captured(gpu_lib):
     g.replay()
     torch.cuda.synchronize()
     st = compare(batch, gold, out, db, 1, label="mixed 8192 planned")
-    tol = TOL[1]
     # ragged trees often have several NCP solutions (validated, not gated)
-    assert st["included"] >= st["n"] // 4
-    assert st["v_max"] <= tol["v"]
-    assert st["jac_max"] <= tol["jac"]
-    assert st["modes_agree"] == st["included"]
-    assert st["alternatives_invalid"] == 0
+    assert_parity(st, min_included=st["n"] // 4, max_flagged=max(1, st["n"] // 20))
     flagged = int(((out["status"].cpu().numpy() & 17) != 0).sum())
     say(f"solver flags over the full batch: {flagged} / {batch.n_env}")
-    assert flagged <= batch.n_env // 6
+    assert flagged <= batch.n_env // 20
 
 
 def test_planned_launch_equals_one_launch(gpu_lib):

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07107_amd import scenes
-from tests.parity_util import TOL, compare, load_golden, say
+from tests.parity_util import TOL, assert_parity, compare, load_golden, say
 
 pytestmark = pytest.mark.gpu
 
@@ -28,42 +28,41 @@ def _run(name, precision, threads=0):
 def test_jacobian_parity(name, precision, gpu_lib):
     gold, batch, db, out = _run(name, precision)
     st = compare(batch, gold, out, db, precision, label=f"{name} p{precision}")
-    tol = TOL[precision]
-    assert st["included"] >= max(1, st["n"] // 3), "too few comparable environments"
-    assert st["v_max"] <= tol["v"]
-    assert st["jac_max"] <= tol["jac"]
-    assert st["modes_agree"] == st["included"]
-    assert st["alternatives_invalid"] == 0
-    assert st["solver_flags"] <= max(1, st["n"] // 10)
+    assert_parity(st, min_included=max(1, st["n"] // 3), max_flagged=max(1, st["n"] // 20))
 
 
-@pytest.mark.parametrize("name,precision", [("arm7_4096_sample", 1), ("tree36_16384_sample", 1),
-                                            ("tree36_16384_sample", 0)])
+@pytest.mark.parametrize("name,precision", [("arm7_4096_sample", 1), ("arm7_4096_sample", 0),
+                                            ("tree36_16384_sample", 1), ("tree36_16384_sample", 0)])
 def test_full_size_sampled_parity(name, precision, gpu_lib):
-    """Full batch in the benchmark's launch configuration, sampled outputs."""
+    """Full batch in the benchmark's launch configuration, 64 environments
+    spread over it compared with the oracle; the solver's failure share over
+    the whole batch at most 1/20 (about 1% measured on tree36)."""
     gold, batch, db, out = _run(name, precision)
     st = compare(batch, gold, out, db, precision, label=f"{name} p{precision}")
-    tol = TOL[precision]
-    assert st["included"] >= st["n"] // 2
-    assert st["v_max"] <= tol["v"]
-    assert st["jac_max"] <= tol["jac"]
-    assert st["modes_agree"] == st["included"]
-    assert st["alternatives_invalid"] == 0
+    assert_parity(st, min_included=st["n"] // 2, max_flagged=max(1, st["n"] // 20))
     status = out["status"].cpu().numpy()
     flagged = int(((status & 17) != 0).sum())
     say(f"solver flags over the full batch: {flagged} / {batch.n_env}")
-    # some random trees give NCPs that neither this solver nor the oracle's
-    # solves (see DESIGN.md); they are flagged, not silently wrong
-    assert flagged <= batch.n_env // 8
+    assert flagged <= batch.n_env // 20
 
 
-@pytest.mark.parametrize("threads", [64, 256])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hard_contact_problems_parity(precision, gpu_lib):
+    """Environments of the full tree36 batch whose NCP the oracle's plain
+    sweeps, mode Newton and active-set search do not finish (its fallback
+    does): the GPU solves them to the oracle's solution."""
+    gold, batch, db, out = _run("tree36_hard", precision)
+    st = compare(batch, gold, out, db, precision, label=f"tree36_hard p{precision}")
+    assert_parity(st, min_included=st["n"] // 3, max_flagged=st["n"] // 6)
+
+
+@pytest.mark.parametrize("threads", [64, 256, 512])
 def test_team_size_invariance(threads, gpu_lib):
     """Results do not depend on the team size beyond rounding."""
     import torch
     gold, batch, db, out = _run("tree36_24", 0, threads=threads)
     st = compare(batch, gold, out, db, 0, label=f"tree36 threads {threads}")
-    assert st["jac_max"] <= TOL[0]["jac"]
+    assert_parity(st, min_included=st["n"] // 2)
 
 
 def test_mixed_batch_matches_separate_runs(gpu_lib):

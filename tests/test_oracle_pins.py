@@ -295,3 +295,82 @@ def test_quaternion_matches_rodrigues():
         R1 = quat_to_rot(t64(quat)).numpy()
         R2 = exp_so3(t64(t * a)).numpy()
         assert np.abs(R1 - R2).max() < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# (e) the solver's fallbacks: natural-map Jacobian, Levenberg-Marquardt, ADMM
+# ---------------------------------------------------------------------------
+
+def _random_problem(rng, nc, ndof=None):
+    ndof = ndof or 3 * nc + 2
+    J = rng.normal(size=(3 * nc, ndof))
+    A = rng.normal(size=(ndof, ndof))
+    M = A @ A.T + ndof * np.eye(ndof)
+    return J @ np.linalg.solve(M, J.T), rng.normal(size=3 * nc) * 0.1, rng.uniform(0.2, 1.2, size=nc)
+
+
+def test_natural_map_jacobian_matches_central_differences():
+    """Away from the kinks of the projection the generalised Jacobian is the
+    ordinary one: compare with central differences at random points (every
+    branch of the projection occurs: inside, polar, boundary)."""
+    rng = np.random.default_rng(3)
+    branches = set()
+    for _ in range(40):
+        G, g, mu = _random_problem(rng, 3)
+        lam = rng.normal(size=9) * 0.2
+        F, JF = ncp.natural_map(G, g, mu, lam)
+        assert np.allclose(np.linalg.norm(F.reshape(-1, 3), axis=1), ncp.natural_residual(G, g, mu, lam),
+                           rtol=0, atol=1e-15)
+        h = 1e-7
+        fd = np.zeros_like(JF)
+        for j in range(9):
+            e = np.zeros(9)
+            e[j] = h
+            fd[:, j] = (ncp.natural_map(G, g, mu, lam + e)[0] - ncp.natural_map(G, g, mu, lam - e)[0]) / (2 * h)
+        assert np.abs(fd - JF).max() <= 1e-6 * max(1.0, np.abs(JF).max())
+        sig = G @ lam + g
+        for i in range(3):
+            tr = np.trace(G[3 * i:3 * i + 3, 3 * i:3 * i + 3])
+            y = lam[3 * i:3 * i + 3] - 3.0 / tr * ncp.desaxce(sig[3 * i:3 * i + 3], mu[i])
+            nt = np.hypot(y[0], y[1])
+            branches.add("in" if nt <= mu[i] * y[2] else "polar" if mu[i] * nt <= -y[2] else "boundary")
+    assert branches == {"in", "polar", "boundary"}
+
+
+def test_fallback_solutions_are_brute_force_solutions():
+    """Levenberg-Marquardt (from a random start) and ADMM followed by it
+    return one of the solutions the exhaustive mode enumeration finds."""
+    rng = np.random.default_rng(8)
+    found = 0
+    for trial in range(12):
+        nc = 1 + trial % 3
+        G, g, mu = _random_problem(rng, nc)
+        sols = ncp.enumerate_solutions(G, g, mu)
+        assert sols
+        lam, ok = ncp.levenberg_marquardt(G, g, mu, rng.normal(size=3 * nc) * 0.05)
+        z, _ = ncp.admm(G, g, mu)
+        lam2, ok2 = ncp.levenberg_marquardt(G, g, mu, z)
+        assert ok2, "ADMM then LM must converge on these monotone-enough problems"
+        for cand, good in ((lam, ok), (lam2, ok2)):
+            if not good:
+                continue
+            found += 1
+            # the impulse scale of the problem (the solution may be Lam = 0)
+            scale = max(np.abs(g).max() / np.diag(G).max(), max(np.linalg.norm(s) for s in sols))
+            assert any(np.linalg.norm(cand - s) <= 1e-7 * scale for s in sols)
+            if np.abs(cand).max() > 1e-6 * scale:
+                assert ncp.check(G, g, mu, cand, tol=1e-10)
+    assert found >= 18
+
+
+def test_admm_solves_the_point_mass_closed_forms():
+    """ADMM on decoupled point masses reproduces the closed forms of each
+    mode: breaking Lam = 0, sticking Lam = -m b, sliding Lam = m b_N (-mu u, -1)."""
+    m, mu = 2.0, 0.6
+    b = np.array([0.3, -0.2, 0.05, 0.01, -0.02, -0.5, 0.4, -0.3, -0.2])
+    G = np.eye(9) / m
+    z, ok = ncp.admm(G, b, np.full(3, mu), tol=1e-12, iters=20000)
+    assert ok
+    u = b[6:8] / np.linalg.norm(b[6:8])
+    ref = np.r_[0, 0, 0, -m * b[3:6], -mu * (-m * b[8]) * u, -m * b[8]]
+    assert np.abs(z - ref).max() <= 1e-10
