@@ -1,13 +1,18 @@
 """Benchmark: step-derivative evaluations per second on one MI355X.
 
-One step = one launch over the whole batch computing, per environment, the
+One step = one call over the whole batch computing, per environment, the
 contact step and its full Jacobian dv+/d(dq, v, tau) (the quantity timed by
-the paper's timing table).  Workload: the 36-dof tree (free flyer + 5
-branches of 6 revolute joints) with 8 foot contacts, 16384 environments,
-FP32 bulk arithmetic with the FP64 reduced-system factorisation and residual
-check.  The same batch is also run in the plain FP64 form.
+the paper's timing table): the step launch (first pass, then the fallback
+pass for the environments it left unsolved) and the derivative launch.
+Workload: the 36-dof tree (free flyer + 5 branches of 6 revolute joints)
+with 8 foot contacts, 16384 environments, in the FP32 form (FP32 contact
+quantities, sweeps and derivative products; FP64 tree recursions,
+refinement, fallback solvers, residual check and reduced system) and in the
+plain FP64 form; `--workload arm7` runs the 7-dof arm batch the same way.
+Each form's outputs are compared with the oracle's stored results on the
+batch's sampled environments (the line's `accuracy` block).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ...]
 
 Prints one JSON line.  Inputs are resident in device memory before timing.
 """
@@ -30,7 +35,16 @@ if ROOT not in sys.path:
 # FP32 and FP64 vector arithmetic both issue at this rate (the 157.3 TFLOP/s
 # FP32 figure assumes packed dual FP32).
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-WORKLOAD = dict(name="tree36", n_env=16384, seed=0)
+WORKLOADS = {
+    "tree36": dict(name="tree36", n_env=16384, seed=0, golden="tree36_16384_sample",
+                   metric="step-derivative evals/sec (36-dof, 8 contacts), FP32-batched vs FP64 plain",
+                   describe="tree36: free flyer + 5 branches x 6 revolute joints (36 dof), 8 foot contacts "
+                            "(two 4-point patches), dt 1e-3, mu 0.7"),
+    "arm7": dict(name="arm7", n_env=4096, seed=0, golden="arm7_4096_sample",
+                 metric="step-derivative evals/sec (7-dof arm, 4 contacts), FP32-batched vs FP64 plain",
+                 describe="arm7: 7 revolute joints with random axes, links U(0.1, 0.4) m, masses U(0.5, 3) kg, "
+                          "4 end-effector contacts, mu ~ U(0.3, 1.0), dt 1e-3"),
+}
 KERNEL = "env_kernel<float, jacobian>"
 STEP_KERNEL = "env_kernel<float, step>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "env_kernel_f32_step_tree36_16384_traffic.json")
@@ -50,20 +64,30 @@ def measured_traffic():
     return float(t["bytes_per_launch"])
 
 
-def algorithmic_flops(batch, modes, sweeps):
+def algorithmic_flops(batch, modes, sweeps, work=None):
     """Per-environment algorithmic FLOP counts, using the tree sparsity (not
     dense n^3), summed over the batch and split by launch: returns
-    (step, derivative, fp64) with the FP64 reduced factorisation and solve
-    counted separately (one FMA = 2 flops).
+    (step, derivative, fp64): the step launches' count includes the FP64
+    fallback pass; fp64 is the derivative launch's FP64 reduced
+    factorisation and solve, counted separately (one FMA = 2 flops).
+    `sweeps` is the Gauss-Seidel sweep count per environment (an array: the
+    sweeps each environment executed, from dsim.solver_work) or one number
+    for all; `work` (dsim.solver_work's dict) adds the fallback pass.
     Step launch: kinematics and dynamics 400 per body; factorisation
     sum d_i^2; Delassus 4 nnzL k + k (k+1) n; contact sweeps
     s (2 k^2 + 50 n_c) + 4 nnzL (n_c + 1).
+    Fallback pass (FP64): per Levenberg-Marquardt iteration the natural-map
+    Jacobian 6 k^2, J^T J k^3 and J^T F 2 k^2; per damped solve the Cholesky
+    k^3 / 3, the solves 2 k^2 and the natural map 2 k^2 + 40 n_c; per ADMM
+    iteration 4 k^2 + 40 n_c, plus k^3 / 3 + 2 k^3 for (G + rho I)^-1 when
+    it ran.
     Derivative launch: the same tree and Delassus work again (it restores the
     step), partial derivatives of inverse dynamics 150 nnzL, fixed-impulse
     derivative 4 nnzL p, right-hand side 2 nnzJ p + 6 k, assembly
     2 nnzJ p + 4 nnzL p, and in FP64 the factorisation m^3/3 + 2/3 (2 n_sld)^3
     and solve 2 m^2 p, with p = 3 n."""
     fs = fd = f64 = 0.0
+    sw = np.broadcast_to(np.asarray(sweeps, dtype=np.float64), (batch.n_env,))
     for e in range(batch.n_env):
         b0, b1 = batch.body_off[e], batch.body_off[e + 1]
         c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
@@ -89,10 +113,59 @@ def algorithmic_flops(batch, modes, sweeps):
         m = 3 * nstk + 2 * nsld
         p = 3 * n
         tree = 400 * nb + (d * d).sum() + 4 * nnzL * k + k * (k + 1) * n
-        fs += tree + sweeps * (2 * k * k + 50 * nc) + 4 * nnzL * (nc + 1)
+        fs += tree + sw[e] * (2 * k * k + 50 * nc) + 4 * nnzL * (nc + 1)
+        if work is not None:
+            it, so, ad = (float(work[x][e]) for x in ("lm_iterations", "lm_solves", "admm_iterations"))
+            fs += it * (8 * k * k + k ** 3) + so * (k ** 3 / 3 + 4 * k * k + 40 * nc)
+            fs += ad * (4 * k * k + 40 * nc) + (k ** 3 / 3 + 2 * k ** 3 if ad > 0 else 0.0)
         fd += tree + 150 * nnzL + 4 * nnzL * p + 2 * nnzJ * p + 6 * k + 2 * nnzJ * p + 4 * nnzL * p
         f64 += m ** 3 / 3 + (2.0 / 3.0) * (2 * nsld) ** 3 + 2 * m * m * p
     return fs, fd, f64
+
+
+def accuracy(batch, db, out, precision, golden):
+    """Error of every output against the oracle's stored results on the
+    sampled environments of `golden` (written by tests/golden/make_golden.py
+    from the oracle alone): per output the max, p99 and median over the
+    environments the parity tests gate, with the category counts."""
+    import contextlib
+    import io
+    from tests import parity_util
+    from oracle import ncp
+    gold = parity_util.golden_for(golden, precision)
+    with contextlib.redirect_stdout(io.StringIO()):
+        st = parity_util.compare(batch, gold, out, db, precision, label=golden)
+    rows = [r for r in st["rows"] if r["cat"] in ("gated", "near")]
+    lam_all = out["lam"].double().cpu().numpy()
+    res = []
+    for gi, e in enumerate(gold["envs"]):
+        e = int(e)
+        if not any(r["env"] == e for r in rows):
+            continue
+        c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
+        lam = lam_all[3 * c0:3 * c1]
+        if c1 > c0:
+            res.append(float(ncp.natural_residual(gold["G"][gi], gold["g"][gi], gold["mu"][gi], lam).max()
+                             / max(np.abs(lam).max(), 1e-300)))
+
+    def stats(x):
+        x = np.asarray(x, dtype=np.float64)
+        return {"max": float(x.max()), "p99": float(np.percentile(x, 99)), "median": float(np.median(x))} \
+            if x.size else None
+
+    return {
+        "reference": f"FP64 oracle, {st['n']} sampled environments of the batch ("
+                     f"{'float32-rounded inputs' if precision == 1 else 'FP64 inputs'})",
+        "gated": st["gated"], "near_switch": st["near"], "conditioned": st["conditioned"],
+        "unpinned": st["unpinned"], "other_valid_solutions": st["alternatives"],
+        "solver_flagged": st["solver_flags"], "failures": len(st["failures"]),
+        "v_next": stats([r["ev"] for r in rows]), "JtLam": stats([r["ejtl"] for r in rows]),
+        "ncp_residual": stats(res),
+        "jac_dq": stats([r["ej"][0] for r in rows if r["ej"]]),
+        "jac_dv": stats([r["ej"][1] for r in rows if r["ej"]]),
+        "jac_dtau": stats([r["ej"][2] for r in rows if r["ej"]]),
+        "jac_elementwise": stats([max(r["ee"]) for r in rows if r["ee"]]),
+    }
 
 
 def _oracle_init():
@@ -109,7 +182,7 @@ def _oracle_one(env):
     return 1
 
 
-def cpu_baseline(batch, cores, per_core=2):
+def cpu_baseline(batch, cores, per_core=8):
     """The FP64 oracle (step + implicit-function-theorem Jacobian), timed on
     the host cores on a bounded sample of the same workload: per_core
     environments per worker process, evenly spaced over the batch."""
@@ -131,7 +204,8 @@ def run(args):
     from paper_2409_07107_amd import dsim, scenes
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
-    batch = scenes.make(WORKLOAD["name"], WORKLOAD["n_env"], seed=WORKLOAD["seed"])
+    wl = WORKLOADS[args.workload]
+    batch = scenes.make(wl["name"], wl["n_env"], seed=wl["seed"])
     results = {}
     runs = [(dsim.F32, args.steps)] + ([] if args.only_f32 else [(dsim.F64, max(3, args.steps // 4))])
     for prec, steps in runs:
@@ -161,11 +235,16 @@ def run(args):
             ends[i].record()
         torch.cuda.synchronize()
         step_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+        # outputs and executed solver work of the last timed call
+        out = dsim.step_jacobian(db, p=p, out=out)
+        torch.cuda.synchronize()
+        work = dsim.solver_work(db, p)
         status = out["status"].cpu().numpy()
         modes = out["mode"].cpu().numpy()
+        acc = accuracy(batch, db, out, prec, wl["golden"]) if not args.only_f32 else None
         results[prec] = dict(wall=wall, steps=steps, kern_ms=kern_ms, step_ms=step_ms, status=status, modes=modes,
                              lds=db.lds_bytes(p, dsim.ENTRY_JACOBIAN), lds_step=db.lds_bytes(p, dsim.ENTRY_STEP),
-                             sweeps=p.ncp_sweeps)
+                             sweeps=p.ncp_sweeps, work=work, accuracy=acc)
         print(f"[bench] precision {prec}: {steps} steps, {wall / steps * 1e3:.3f} ms/step, "
               f"launches {kern_ms:.3f} ms (step {step_ms:.3f} ms), flagged {int(((status & 17) != 0).sum())}",
               file=sys.stderr, flush=True)
@@ -175,38 +254,51 @@ def run(args):
     n = batch.n_env
     value = n * r32["steps"] / r32["wall"]
     fp64_value = n * r64["steps"] / r64["wall"]
-    fs, fd, f64 = algorithmic_flops(batch, r32["modes"], r32["sweeps"])
+    w32 = r32["work"]
+    fs, fd, f64 = algorithmic_flops(batch, r32["modes"], w32["sweeps"], w32)
+    flagged32 = int(((r32["status"] & 17) != 0).sum())
+    flagged64 = int(((r64["status"] & 17) != 0).sum())
     deriv_ms = r32["kern_ms"] - r32["step_ms"]
-    kernels = [dict(kernel=STEP_KERNEL, ms=r32["step_ms"], algorithmic_flops=fs, lds_bytes=r32["lds_step"],
-                    tflops=fs / (r32["step_ms"] * 1e-3) / 1e12),
+    kernels = [dict(kernel=STEP_KERNEL, launches="first pass + fallback pass", ms=r32["step_ms"],
+                    algorithmic_flops=fs, lds_bytes=r32["lds_step"], tflops=fs / (r32["step_ms"] * 1e-3) / 1e12),
                dict(kernel=KERNEL, ms=deriv_ms, algorithmic_flops=fd + f64, lds_bytes=r32["lds"],
                     tflops=(fd + f64) / (deriv_ms * 1e-3) / 1e12)]
     dom = max(kernels, key=lambda x: x["ms"])
     achieved = dom["tflops"]
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.workload == "tree36" else None
     cores = int(os.environ.get("BENCH_CPU_CORES", min(16, os.cpu_count() or 1)))
     cpu = None if args.no_cpu else cpu_baseline(batch, cores)
     line = {
-        "metric": "step-derivative evals/sec (36-dof, 8 contacts), FP32-batched vs FP64 plain",
+        "metric": wl["metric"],
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": r32["steps"], "warmup": args.warmup,
         "ms_per_step": r32["wall"] / r32["steps"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "tree36: free flyer + 5 branches x 6 revolute joints (36 dof), 8 foot contacts "
-                               "(two 4-point patches), dt 1e-3, mu 0.7; one step + full Jacobian dv+/d(q,v,tau) "
-                               "per env; FP32 bulk with FP64 reduced factorisation and residual",
-                   "n_env": n, "seed": WORKLOAD["seed"], "entry": "dsim_step_jacobian"},
+        "config": {"workload": wl["describe"] + "; one step + full Jacobian dv+/d(q,v,tau) per env. FP32 form: "
+                               "contact Jacobian, Delassus G and g, Gauss-Seidel sweeps and the derivative "
+                               "products in FP32 (FP64 sums); FP64: tree recursions (kinematics, M, its "
+                               "factorisation and inverse, inverse-dynamics partials), Newton refinement, "
+                               "fallback solvers, natural-map residual check, reduced-system factorisation "
+                               "and solve",
+                   "n_env": n, "seed": wl["seed"], "entry": "dsim_step_jacobian"},
+        "converged_evals_per_s": value * (n - flagged32) / n,
         "fp64_plain": {"value": fp64_value, "unit": "evals/s", "steps": r64["steps"],
-                       "ms_per_step": r64["wall"] / r64["steps"] * 1e3, "fp32_over_fp64": value / fp64_value},
+                       "ms_per_step": r64["wall"] / r64["steps"] * 1e3, "fp32_over_fp64": value / fp64_value,
+                       "converged_evals_per_s": fp64_value * (n - flagged64) / n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
                      "kernel": dom["kernel"], "kernel_ms": dom["ms"],
                      "algorithmic_flops_per_launch": dom["algorithmic_flops"], "lds_bytes_per_team": dom["lds_bytes"],
                      "both_launches": {"ms": r32["kern_ms"], "algorithmic_flops": fs + fd + f64,
-                                       "fp64_flops": f64, "tflops": (fs + fd + f64) / (r32["kern_ms"] * 1e-3) / 1e12},
+                                       "derivative_fp64_flops": f64, "tflops": (fs + fd + f64) / (r32["kern_ms"] * 1e-3) / 1e12},
                      "kernels": kernels},
+        "solver_work": {"sweeps_executed": {"mean": float(w32["sweeps"].mean()), "max": int(w32["sweeps"].max()),
+                                            "configured_per_round": r32["sweeps"]},
+                        "fallback_envs": int((w32["lm_iterations"] > 0).sum()),
+                        "lm_iterations": int(w32["lm_iterations"].sum()), "lm_solves": int(w32["lm_solves"].sum()),
+                        "admm_iterations": int(w32["admm_iterations"].sum())},
+        "accuracy": {"fp32": r32["accuracy"], "fp64": r64["accuracy"]},
         "cpu_baseline": cpu,
-        "status_flagged": {"fp32": int(((r32["status"] & 17) != 0).sum()),
-                           "fp64": int(((r64["status"] & 17) != 0).sum())},
+        "status_flagged": {"fp32": flagged32, "fp64": flagged64},
     }
     print(json.dumps(line), flush=True)
 
@@ -412,9 +504,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-f32", action="store_true",
                     help="time only the FP32 launch and print no JSON line (for profiler runs)")
-    ap.add_argument("--workload", choices=("tree36", "mixed", "rollout", "params", "spheres"), default="tree36",
-                    help="tree36 (the headline line), the ragged mixed batch, 200-step rollouts, or the reverse "
-                         "mode with physical-parameter gradients")
+    ap.add_argument("--workload", choices=("tree36", "arm7", "mixed", "rollout", "params", "spheres"),
+                    default="tree36",
+                    help="tree36 (the headline line), the 7-dof arm batch, the ragged mixed batch, 200-step "
+                         "rollouts, or the reverse mode with physical-parameter gradients")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="run one plain copy of BYTES and exit (counter calibration)")
     args = ap.parse_args()

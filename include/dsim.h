@@ -197,13 +197,24 @@ int32_t dsim_validate_params(const dsim_params* params);
  * step entries; for the derivative entries (Jacobian, VJP, parameter
  * gradients and the rollout adjoint), which run as two launches on `stream`
  * -- the step, then the derivative -- the hand-over between them: each
- * environment's FP64 contact impulses (504 bytes) and a record of the step's
+ * environment's FP64 contact impulses and solver counts (DSIM_WS_ENV_DOUBLES doubles,
+ * at the start of the workspace) and a record of the step's
  * quantities that the derivative reads (kinematics, inertias, M^-1, the
  * contact rows, the factorised reduced system, v+ and a+), sized by the
  * batch's max_* fields and the precision (about 36 KB for 31 bodies, 36 dofs
  * and 8 contacts in FP32).  The workspace is the caller's; it must not be
  * shared by calls that may run concurrently. */
 size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
+
+/* The workspace of a derivative entry starts with DSIM_WS_ENV_DOUBLES
+ * doubles per environment (environment e at e * DSIM_WS_ENV_DOUBLES): its
+ * FP64 contact impulses (3 n_c), then, from index DSIM_WS_WORK, the work its
+ * contact solve executed in the call: Gauss-Seidel sweeps of the first pass,
+ * Levenberg-Marquardt iterations and damped linear solves, and ADMM
+ * iterations of the fallback pass (Section II.B solvers), as doubles.  Valid
+ * after the call completes, until the workspace is reused. */
+#define DSIM_WS_ENV_DOUBLES 68
+#define DSIM_WS_WORK 63
 
 /* Bytes of on-chip (LDS) storage one environment team uses for `entry`
  * (a dsim_entry).  A call whose team needs more than 160 KiB (the LDS of
@@ -251,6 +262,36 @@ int32_t dsim_step_vjp(const dsim_batch* batch, const dsim_params* params,
                       const void* q, const void* v, const void* tau,
                       const void* g_vnext, const void* g_lam,
                       void* v_next, void* lam, int8_t* mode, int32_t* status,
+                      void* g_q, void* g_v, void* g_tau,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * dsim_step_vjp in two calls, for a caller that takes the step first and
+ * its reverse mode later (an autograd forward and backward): the step
+ * (Section II.C) as dsim_step that also keeps, in `ws`, the hand-over the
+ * reverse mode reads (ws_bytes at least dsim_workspace_bytes for
+ * DSIM_ENTRY_VJP; DSIM_ERR_WORKSPACE otherwise, before any launch) ...
+ */
+int32_t dsim_step_keep(const dsim_batch* batch, const dsim_params* params,
+                       const void* q, const void* v, const void* tau,
+                       void* v_next, void* lam, int8_t* mode, int32_t* status,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ... then the reverse mode of that step (Section III.A, through the
+ * implicit contact system) without solving it again: g_q, g_v, g_tau as
+ * dsim_step_vjp computes them, bit for bit, for the same batch, params, q,
+ * v and tau, reading the kept hand-over from `ws` and the step's modes from
+ * `mode` (its output, unchanged); `status` is the step's status output, to
+ * which DSIM_ST_NONFINITE is added if a gradient is not finite.  The
+ * workspace must not be reused or written between the two calls; several
+ * reverse passes may read one kept step.  One launch on `stream`, which
+ * must be ordered after the dsim_step_keep call.
+ */
+int32_t dsim_vjp_kept(const dsim_batch* batch, const dsim_params* params,
+                      const void* q, const void* v, const void* tau,
+                      const void* g_vnext, const void* g_lam,
+                      const int8_t* mode, int32_t* status,
                       void* g_q, void* g_v, void* g_tau,
                       void* ws, size_t ws_bytes, void* stream);
 

@@ -2,8 +2,9 @@
 
 forward runs `dsim_step`; backward runs `dsim_step_vjp`, the library's
 reverse mode through the implicit contact system (Section III.A), which
-recomputes the step from the saved inputs instead of storing its internals,
-and `dsim_tangent_to_ambient` to express the q gradient in the stored
+recomputes the step from the saved inputs instead of storing its internals
+(or, with keep, forward runs `dsim_step_keep` and backward `dsim_vjp_kept`,
+which reads the kept step), and `dsim_tangent_to_ambient` to express the q gradient in the stored
 coordinates of q.  Gradients flow to q, v and tau from both outputs, v+
 and the contact impulses.
 
@@ -19,16 +20,25 @@ from . import dsim
 
 
 class DiffStep(torch.autograd.Function):
-    """v_next, lam = DiffStep.apply(q, v, tau, device_batch, params).  Both
-    outputs are differentiable; the impulse gradient uses the library's
-    impulse derivative, one valid choice when contacts are redundant."""
+    """v_next, lam = DiffStep.apply(q, v, tau, device_batch, params, keep).
+    Both outputs are differentiable; the impulse gradient uses the library's
+    impulse derivative, one valid choice when contacts are redundant.  With
+    keep, forward keeps the step's hand-over (`dsim_step_keep`, one
+    workspace per call, about 36 KB per 36-dof environment) and backward
+    runs only the reverse mode (`dsim_vjp_kept`); without, backward solves
+    the step again (`dsim_step_vjp`) and forward stores only its inputs."""
 
     @staticmethod
-    def forward(ctx, q, v, tau, db, p):
+    def forward(ctx, q, v, tau, db, p, keep=False):
         for name, t in (("q", q), ("v", v), ("tau", tau)):
             if t.dtype != db.dtype or not t.is_contiguous() or t.device.type != db.device.type:
                 raise ValueError(f"{name} must be a contiguous {db.dtype} tensor on {db.device}")
-        out = dsim.step(db, q.detach(), v.detach(), tau.detach(), p)
+        if keep:
+            out = dsim.step_keep(db, q.detach(), v.detach(), tau.detach(), p)
+            ctx.kept = out
+        else:
+            out = dsim.step(db, q.detach(), v.detach(), tau.detach(), p)
+            ctx.kept = None
         ctx.save_for_backward(q.detach(), v.detach(), tau.detach())
         ctx.db, ctx.p = db, p
         return out["v_next"], out["lam"]
@@ -37,20 +47,24 @@ class DiffStep(torch.autograd.Function):
     def backward(ctx, g_vnext, g_lam):
         q, v, tau = ctx.saved_tensors
         if g_vnext is None and g_lam is None:
-            return None, None, None, None, None
+            return None, None, None, None, None, None
         if g_vnext is None:
             g_vnext = torch.zeros_like(v)
         gl = None
         if g_lam is not None and ctx.db.n_contact > 0:
             gl = g_lam.contiguous()
-        o = dsim.step_vjp(ctx.db, g_vnext.contiguous(), q, v, tau, ctx.p, g_lam=gl)
+        if ctx.kept is not None:
+            o = dsim.vjp_kept(ctx.db, ctx.kept, g_vnext.contiguous(), q, v, tau, ctx.p, g_lam=gl)
+        else:
+            o = dsim.step_vjp(ctx.db, g_vnext.contiguous(), q, v, tau, ctx.p, g_lam=gl)
         g_q = dsim.tangent_to_ambient(ctx.db, q, o["g_q"]) if ctx.needs_input_grad[0] else None
-        return g_q, o["g_v"], o["g_tau"], None, None
+        return g_q, o["g_v"], o["g_tau"], None, None, None
 
 
-def diff_step(db, q, v, tau, p=None):
-    """Differentiable step: returns (v_next, lam)."""
-    return DiffStep.apply(q, v, tau, db, p or db.params())
+def diff_step(db, q, v, tau, p=None, keep=False):
+    """Differentiable step: returns (v_next, lam).  keep: backward reuses the
+    forward's solve instead of solving the step again (more memory)."""
+    return DiffStep.apply(q, v, tau, db, p or db.params(), keep)
 
 
 def _param_batch(db, mass, inertia, mu):

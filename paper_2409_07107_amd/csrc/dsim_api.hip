@@ -13,6 +13,9 @@
 
 using namespace dsim;
 
+static_assert(kLdStride == DSIM_WS_ENV_DOUBLES && kLdWork == DSIM_WS_WORK,
+              "the documented layout of the impulse hand-over");
+
 namespace {
 
 constexpr size_t kLdsLimit = 160 * 1024;  // bytes of LDS per workgroup on gfx950
@@ -290,6 +293,29 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
                                 stream);
 }
 
+// The halves of a derivative entry as separate calls: the step launches
+// writing the hand-over into `ws` (half 1), or the derivative launch reading
+// it (half 2) -- the same launches, in the same order, as the whole entry.
+template <class R, int ENTRY>
+int launch_half(int half, const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                const void* tau, const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode,
+                int32_t* status, void* o1, void* o2, void* o3, void* ws, size_t ws_bytes, void* stream) {
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!ws || ws_bytes < handover_bytes(b, p)) return DSIM_ERR_WORKSPACE;
+    if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
+    double* ld = static_cast<double*>(ws);
+    if (half == 1) {
+        for (int pass = 0; pass < 2; ++pass) {
+            int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status,
+                                               nullptr, nullptr, nullptr, nullptr, nullptr, ld, stream, pass);
+            if (rc) return rc;
+        }
+        return DSIM_SUCCESS;
+    }
+    return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, nullptr,
+                                nullptr, ld, stream);
+}
+
 template <int ENTRY>
 int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
              const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
@@ -496,6 +522,35 @@ int32_t dsim_step_vjp(const dsim_batch* b, const dsim_params* p, const void* q, 
     if (!g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
     return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, g_lam, v_next, lam, mode, status, g_q, g_v, g_tau,
                                nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int32_t dsim_step_keep(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+                       void* v_next, void* lam, int8_t* mode, int32_t* status, void* ws, size_t ws_bytes,
+                       void* stream) {
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !v || !tau || !v_next || !status || !mode || !lam) return DSIM_ERR_ARG;
+    if (p->precision == DSIM_F32)
+        return launch_half<float, ENTRY_VJP>(1, b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status,
+                                             nullptr, nullptr, nullptr, ws, ws_bytes, stream);
+    return launch_half<double, ENTRY_VJP>(1, b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                          nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int32_t dsim_vjp_kept(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+                      const void* g_vnext, const void* g_lam, const int8_t* mode, int32_t* status, void* g_q,
+                      void* g_v, void* g_tau, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !v || !tau || !status || !mode || !g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
+    int8_t* md = const_cast<int8_t*>(mode);  // read only by the derivative launch
+    if (p->precision == DSIM_F32)
+        return launch_half<float, ENTRY_VJP>(2, b, p, q, v, tau, g_vnext, g_lam, nullptr, nullptr, md, status, g_q,
+                                             g_v, g_tau, ws, ws_bytes, stream);
+    return launch_half<double, ENTRY_VJP>(2, b, p, q, v, tau, g_vnext, g_lam, nullptr, nullptr, md, status, g_q,
+                                          g_v, g_tau, ws, ws_bytes, stream);
 }
 
 int32_t dsim_step_vjp_params(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,

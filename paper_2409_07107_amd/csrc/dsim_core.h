@@ -159,8 +159,12 @@ enum { BRK = 0, STK = 1, SLD = 2 };
 // coefficients; the step, its Jacobian and the parameter columns
 enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4, ENTRY_PVJP = 5, ENTRY_PJAC = 6 };
 // FP64 impulses handed from the step launch to the derivative launch: one
-// slot of 3 x (maximum contacts) per environment
-constexpr int kLdStride = 63;
+// slot of 3 x (maximum contacts) per environment, followed by the work its
+// contact solve executed (read back for the flop count): Gauss-Seidel
+// sweeps of the first pass, Levenberg-Marquardt iterations and linear
+// solves and ADMM iterations of the fallback pass
+constexpr int kLdWork = 63;
+constexpr int kLdStride = 68;
 
 DSIM_HD inline bool entry_has_derivative(int entry) {
     return entry == ENTRY_JAC || entry == ENTRY_VJP || entry == ENTRY_RVJP || entry == ENTRY_PVJP ||

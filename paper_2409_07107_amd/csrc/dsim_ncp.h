@@ -270,6 +270,7 @@ DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
                 }
                 T.wave_sync();
             }
+            if (T.lane == 0) E.hdr[7] += 1;  // sweeps executed
             if (!moved) break;
         }
     }
@@ -752,6 +753,29 @@ DSIM_INLINE DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
         for (int i = T.tid; i < m; i += T.nt) E.Ld[3 * E.vctc[i] + E.vcmp[i]] += E.X[i];
         T.sync();
     }
+    if (ok && P.ncp_tol > 1e-9) {
+        // A loose tolerance (the FP32 form's) stops the refinement one step
+        // short of what FP64 Newton reaches on the converged mode set, and
+        // the derivative inherits the solution's error through the reduced
+        // system: take one more step (the system of the last evaluation is
+        // current) and keep it when the residual decreases.
+        const int m = E.hdr[1];
+        const double res0 = E.dsc[1];
+        for (int r = T.tid; r < k; r += T.nt) E.Ld1[r] = E.Ld[r];
+        T.sync();
+        factor_A(T, E, P.rank_tol);
+        if (T.tid == 0) lu_solve(E.A, m, E.hdr[4], E.rperm, E.cperm, E.rhs, E.ytmp, E.X);
+        T.sync();
+        for (int i = T.tid; i < m; i += T.nt) E.Ld[3 * E.vctc[i] + E.vcmp[i]] += E.X[i];
+        T.sync();
+        fp64_sigma(T, E);
+        newton_system(T, E, P);
+        if (!(E.dsc[1] < res0)) {
+            for (int r = T.tid; r < k; r += T.nt) E.Ld[r] = E.Ld1[r];
+            T.sync();
+            fp64_sigma(T, E);
+        }
+    }
     if (T.tid == 0) E.hdr[6] = ok ? 1 : 0;
     T.sync();
     return ok;
@@ -978,6 +1002,7 @@ DSIM_HD bool lm_solve(const Team& T, Env<R>& E, double tol, double accept, int m
     int solves = 0, since = 0;
     bool stop = false;
     for (int it = 0; it < max_it && !stop; ++it) {
+        if (T.tid == 0) E.hdr[8] += 1;  // iterations executed
         natural_map(T, E, E.Ld, F, true, pm, cm);
         const double f2 = E.dsc[8], fmax = E.dsc[9], lmax = E.dsc[10];
         if (fmax <= tol * lmax) return true;
@@ -1018,6 +1043,7 @@ DSIM_HD bool lm_solve(const Team& T, Env<R>& E, double tol, double accept, int m
                 stop = true;  // the final evaluation at Ld decides
                 break;
             }
+            if (T.tid == 0) E.hdr[3] += 1;  // damped solves executed
             const double floor = 1e-12 * tr / k;
             for (int idx = T.tid; idx < k * k; idx += T.nt) {
                 const int i = idx / k, j = idx - i * k;
@@ -1097,6 +1123,7 @@ DSIM_HD bool admm_solve(const Team& T, Env<R>& E, double tol, int max_it, int ch
     }
     T.sync();
     for (int it = 0; it < max_it; ++it) {
+        if (T.tid == 0) E.hdr[15] += 1;  // iterations executed
         // L = Minv (rho (z - u) - g - s)
         for (int r = T.tid; r < k; r += T.nt) E.X[r] = rho * (z[r] - u[r]) - E.gd[r] - sv[r];
         T.sync();

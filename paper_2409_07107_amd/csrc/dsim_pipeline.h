@@ -922,6 +922,15 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
         if (ld) {
             double* l = ld + size_t(E.e) * kLdStride;
             for (int r = T.tid; r < E.k; r += T.nt) l[r] = E.Ld[r];
+            if (T.tid == 0) {
+                // executed solver work: the first pass writes its sweeps and
+                // clears the fallback's counts, the fallback pass (run only
+                // for the environments the first left unsolved) writes its own
+                if (P.pass == 0) l[kLdWork] = double(E.hdr[7]);
+                l[kLdWork + 1] = double(E.hdr[8]);
+                l[kLdWork + 2] = double(E.hdr[3]);
+                l[kLdWork + 3] = double(E.hdr[15]);
+            }
         }
         if (entry == ENTRY_SINT) integrate(T, E, P, q, o1);
     } else {
@@ -939,6 +948,34 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
             vjp(T, E, B, P, gbar, static_cast<const R*>(nullptr), gbar2, o1, o2, o3);
             param_grads(T, E, P, o4);
         }
+        // a NaN or Inf in the derivative outputs sets the status bit that
+        // the step sets for its own outputs
+        const int n = E.nv, np = 7 * E.nb + E.nc;
+        bool bad = false;
+        auto scan = [&](const R* p, size_t off, int cnt) {
+            if (!p) return;
+            for (int i = T.tid; i < cnt; i += T.nt) {
+                const double x = double(p[off + i]);
+                if (!(x == x) || fabs(x) > 1e300) bad = true;
+            }
+        };
+        if (entry == ENTRY_JAC || entry == ENTRY_PJAC) {
+            const size_t off = size_t(B.jac_off[e]);
+            scan(o1, off, n * n);
+            scan(o2, off, n * n);
+            scan(o3, off, n * n);
+            if (entry == ENTRY_PJAC) scan(o4, size_t(B.pjac_off[e]), n * np);
+        } else {
+            scan(o1, size_t(E.d0), n);
+            scan(o2, size_t(E.d0), n);
+            scan(o3, size_t(E.d0), n);
+            if (entry == ENTRY_PVJP) scan(o4, 7 * size_t(E.b0) + E.c0, np);
+        }
+        if (T.tid == 0) E.hdr[11] = 0;
+        T.sync();
+        if (bad) E.hdr[11] = 1;
+        T.sync();
+        if (T.tid == 0 && E.hdr[11]) status[e] |= ST_NONFINITE;
     }
     T.sync();
 }

@@ -22,15 +22,20 @@ DSIM_HD void load_env(const Team& T, Env<R>& E, const BatchView<R>& B, int e, co
     E.nq = B.cfg_off[e + 1] - E.q0;
     E.nc = B.contact_off[e + 1] - E.c0;
     E.k = 3 * E.nc;
+    // the model tables are read by the team at once; the serial pass below
+    // then works from LDS
+    for (int b = T.tid; b < E.nb; b += T.nt) {
+        E.parent[b] = B.parent[E.b0 + b];
+        E.jtype[b] = B.jtype[E.b0 + b];
+    }
+    T.sync();
     if (T.tid == 0) {
         const int nb = E.nb;
         int dof = 0, cfg = 0;
         int depth[64];
         for (int b = 0; b < nb; ++b) {
-            const int par = B.parent[E.b0 + b];
-            const int jt = B.jtype[E.b0 + b];
-            E.parent[b] = par;
-            E.jtype[b] = jt;
+            const int par = E.parent[b];
+            const int jt = E.jtype[b];
             E.dof0[b] = dof;
             E.cfg0[b] = cfg;
             const int nd = (jt == 1) ? 6 : 1;

@@ -21,13 +21,15 @@ ENTRY_STEP, ENTRY_JACOBIAN, ENTRY_VJP, ENTRY_STEP_INTEGRATE, ENTRY_STEP_INTEGRAT
 ENTRY_VJP_PARAMS, ENTRY_JACOBIAN_PARAMS = 5, 6
 ST_NCP_NOT_CONVERGED, ST_RANK_DEFICIENT, ST_MODE_DEGENERATE, ST_NONFINITE, ST_POLISH_FAILED = 1, 2, 4, 8, 16
 ST_SIZE_EXCEEDED = 32
+WS_ENV_DOUBLES, WS_WORK = 68, 63  # DSIM_WS_ENV_DOUBLES, DSIM_WS_WORK
 MODE_BREAK, MODE_STICK, MODE_SLIDE = 0, 1, 2
 
 SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim_validate_host",
            "dsim_validate_params", "dsim_workspace_bytes", "dsim_lds_bytes", "dsim_step",
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
            "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params",
-           "dsim_step_jacobian_params", "dsim_ambient_to_tangent", "dsim_status_string")
+           "dsim_step_jacobian_params", "dsim_ambient_to_tangent", "dsim_status_string",
+           "dsim_step_keep", "dsim_vjp_kept")
 
 _vp = ctypes.c_void_p
 
@@ -84,6 +86,12 @@ def lib():
         L.dsim_step_vjp.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 12 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp.restype = ctypes.c_int32
+        L.dsim_step_keep.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 7 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_keep.restype = ctypes.c_int32
+        L.dsim_vjp_kept.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 10 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_vjp_kept.restype = ctypes.c_int32
         L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp_params.restype = ctypes.c_int32
@@ -293,6 +301,64 @@ def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, ou
                            _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
                            _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
     return out
+
+
+def step_keep(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
+    """dsim_step_keep: the step, keeping the hand-over its reverse mode reads
+    in a fresh workspace tensor, out["kept"] (held until the reverse passes
+    through vjp_kept are done)."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    out = out or _outputs(db)
+    c = db.c if cb is None else cb
+    nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(c), ctypes.byref(p), ENTRY_VJP))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=db.device)
+    _check(lib().dsim_step_keep(ctypes.byref(c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau), _ptr(out["v_next"]),
+                                _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]), _ptr(ws),
+                                ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    out["kept"] = ws
+    return out
+
+
+def vjp_kept(db: DeviceBatch, kept, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, g_lam=None,
+             cb=None):
+    """dsim_vjp_kept: the reverse mode of the step `kept` (step_keep's output
+    for the same q, v, tau and params) without solving it again.  Returns
+    g_q, g_v, g_tau and the step's status with DSIM_ST_NONFINITE added for
+    non-finite gradients."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    c = db.c if cb is None else cb
+    out = {k: torch.empty(db.n_dof, dtype=db.dtype, device=db.device) for k in ("g_q", "g_v", "g_tau")}
+    out["status"] = kept["status"].clone()
+    ws = kept["kept"]
+    _check(lib().dsim_vjp_kept(ctypes.byref(c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau), _ptr(g_vnext),
+                               _ptr(g_lam), _ptr(kept["mode"]), _ptr(out["status"]), _ptr(out["g_q"]),
+                               _ptr(out["g_v"]), _ptr(out["g_tau"]), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                               ctypes.c_void_p(_stream())))
+    return out
+
+
+def solver_work(db: DeviceBatch, p: CParams | None = None, entry: int = ENTRY_JACOBIAN, cb=None):
+    """The work each environment's contact solve executed in the last
+    completed call of derivative entry `entry` on this batch's workspace
+    (DSIM_WS_WORK): dict of int arrays sweeps (first-pass Gauss-Seidel),
+    lm_iterations, lm_solves and admm_iterations (fallback pass)."""
+    import torch
+    p = p or db.params()
+    ws, nbytes = db.workspace(p, entry, cb)
+    if ws is None:
+        raise ValueError("entry has no workspace")
+    n = int((db.c if cb is None else cb).n_env)
+    w = ws[:n * WS_ENV_DOUBLES * 8].view(torch.float64).reshape(n, WS_ENV_DOUBLES)
+    a = w[:, WS_WORK:WS_WORK + 4].cpu().numpy().astype(np.int64)
+    return dict(sweeps=a[:, 0], lm_iterations=a[:, 1], lm_solves=a[:, 2], admm_iterations=a[:, 3])
 
 
 def step_jacobian(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):

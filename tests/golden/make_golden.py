@@ -3,13 +3,19 @@ tests/golden/*.npz.  Calls only the oracle (and the seeded scene generator);
 nothing here comes from the HIP path.
 
     python tests/golden/make_golden.py [name ...]
+    python tests/golden/make_golden.py --sensitivity [name_f32in ...]
+
+A name with the suffix "_f32in" stores the same environments computed from
+inputs rounded to float32: the reference of the FP32 form's comparisons.
 
 Each file holds, per listed environment: index, v+ (n_v), J^T Lam (n_v),
 modes (n_c), margin, solver ok flag, whether the solver needed its fallback,
 uniqueness of the v+ derivative, the full Jacobian d v+ / d(dq, v, tau)
 (n_v x 3 n_v), the contact Jacobian J (3 n_c x n_v, to form J^T Lam of a
 GPU impulse) and the NCP data (G, g, mu) so that a different but valid GPU
-solution can be recognised.  The
+solution can be recognised.  The "_f32in" files add, per environment, the
+sensitivity of v+ to float32 rounding of the contact problem's assembly
+(`fp32_sensitivity`), which scales the FP32 form's tolerance.  The
 parameter sets hold the derivatives of v+ in the body masses and friction
 coefficients (n_v x (n_b + n_c)) instead of the Jacobian.
 """
@@ -25,7 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from paper_2409_07107_amd import scenes  # noqa: E402
-from oracle import derivative, rollout, step  # noqa: E402
+from oracle import derivative, ncp, rollout, step  # noqa: E402
 
 def spread(n_env, count, seed):
     """`count` environment indices of an n_env batch: the first and last four
@@ -76,6 +82,20 @@ PARAMS = {
 
 _BATCH = None
 
+# the arrays of a scene batch that hold real numbers (model and state)
+REAL_FIELDS = ("axis", "jrot", "jpos", "mass", "com", "inertia", "cpoint", "mu", "cradius", "q", "v", "tau")
+
+
+def round_to_f32(batch):
+    """The batch with every real input rounded to float32 (and held in
+    float64): the inputs the FP32 form actually receives, so that its
+    comparison with the oracle measures its arithmetic, not the rounding of
+    its inputs."""
+    for f in REAL_FIELDS:
+        a = getattr(batch, f)
+        setattr(batch, f, np.asarray(a, dtype=np.float32).astype(np.float64))
+    return batch
+
 
 def params_inputs(name):
     """The seeded batch of a parameter set (inputs only; shared with the GPU
@@ -119,6 +139,68 @@ def make_params(name):
     print(name, "ok", int(out["ok"].sum()), "/", len(envs), "unique", int(out["unique"].sum()), flush=True)
 
 
+U32 = 2.0 ** -24  # unit roundoff of float32
+
+
+def fp32_sensitivity(env, r, seed, draws=4):
+    """How far v+ moves, relative to the parity tests' v+ scale, under the
+    rounding errors of an FP32 assembly of the contact problem, with G, g,
+    the NCP and v+ then formed and solved in FP64: M, J and v_f perturbed
+    element by element by independent relative errors of size u32, and G,
+    g and v+ by the error bound of a float32 dot product, u32 times the
+    product of the absolute values (|J| |M^-1 J^T| for G, |J| |v_f| for g,
+    |M^-1 J^T| |Lam| for v+), times independent N(0, 1) draws; the impulses
+    solve the perturbed equations of the unperturbed solution's modes (the
+    comparison's premise), by Newton from that solution.  The forward
+    error this environment's conditioning allows an FP32 form; the largest
+    of `draws` seeded draws, at least u32."""
+    M, J, vf, mu = r["M"], r["J"], r["vf"], r["model"].mu
+    if J.shape[0] == 0:
+        return U32
+    rng = np.random.default_rng(seed)
+    k = J.shape[0]
+    gadd = r["g"] - J @ vf  # the gap-mode terms (zero in gap mode 0)
+    scale = max(np.abs(r["vnext"]).max(), np.abs(env["v"]).max(), 9.81 * r["model"].dt)
+    worst = U32
+    for _ in range(draws):
+        Mp = M * (1.0 + U32 * rng.standard_normal(M.shape))
+        Mp = 0.5 * (Mp + Mp.T)
+        Jp = J * (1.0 + U32 * rng.standard_normal(J.shape))
+        vp = vf * (1.0 + U32 * rng.standard_normal(vf.shape))
+        X = np.linalg.solve(Mp, Jp.T)
+        dG = U32 * (np.abs(Jp) @ np.abs(X)) * rng.standard_normal((k, k))
+        G = Jp @ X + 0.5 * (dG + dG.T)
+        G = 0.5 * (G + G.T)
+        g = Jp @ vp + U32 * (np.abs(Jp) @ np.abs(vp)) * rng.standard_normal(k) + gadd
+        Lam = ncp.newton_modes(G, g, mu, r["Lam"], r["modes"], iters=4)
+        vn = vp + X @ Lam + U32 * (np.abs(X) @ np.abs(Lam)) * rng.standard_normal(len(vp))
+        worst = max(worst, float(np.abs(vn - r["vnext"]).max() / scale))
+    return worst
+
+
+def _sens_one(e):
+    env = _BATCH.env(e)
+    return fp32_sensitivity(env, step.forward(env), 7919 + e)
+
+
+def refresh_sensitivity(name):
+    """Recomputes only the "sens" field of an existing "_f32in" file (the
+    same function `make` stores it with)."""
+    global _BATCH
+    assert name.endswith("_f32in")
+    path = os.path.join(HERE, f"{name}.npz")
+    z = np.load(path, allow_pickle=False)
+    out = {k: z[k] for k in z.files}
+    _BATCH = round_to_f32(scenes.make(str(out["workload"]), int(out["n_env"]), seed=int(out["seed"])))
+    with Pool(8) as p:
+        out["sens"] = np.array(p.map(_sens_one, [int(e) for e in out["envs"]]))
+    np.savez_compressed(path, **out)
+    print(name, "sensitivity: median %.1e max %.1e" % (np.median(out["sens"]), out["sens"].max()), flush=True)
+
+
+_F32 = False
+
+
 def _one(e):
     env = _BATCH.env(e)
     r = step.forward(env)
@@ -127,7 +209,8 @@ def _one(e):
                 G=r["G"], g=r["g"], mu=r["model"].mu, J=r["J"],
                 margin=r["margin"], ok=bool(r["info"]["ok"]), unique=bool(d["unique_v"]), jac=d["jac"],
                 residual=float(r["residual"].max()) if len(r["residual"]) else 0.0,
-                fallback=bool(r["info"].get("fallback", False)))
+                fallback=bool(r["info"].get("fallback", False)),
+                sens=fp32_sensitivity(env, r, 7919 + e) if _F32 else 0.0)
 
 
 def _needs_fallback(e):
@@ -136,20 +219,26 @@ def _needs_fallback(e):
 
 
 def make(name):
-    global _BATCH
-    if name in HARD:
-        wl, n, seed, count, limit = HARD[name]
+    """Writes <name>.npz (FP64 inputs) or, for a name ending in "_f32in", the
+    same environments with the inputs rounded to float32."""
+    global _BATCH, _F32
+    base = name[:-len("_f32in")] if name.endswith("_f32in") else name
+    if base in HARD:
+        wl, n, seed, count, limit = HARD[base]
         _BATCH = scenes.make(wl, n, seed=seed)
         with Pool(8) as p:
             flags = p.map(_needs_fallback, range(limit))
         envs = [e for e, f in flags if f][:count]
-        print(name, "scanned", limit, "environments, fallback needed by", sum(f for _, f in flags), flush=True)
+        print(base, "scanned", limit, "environments, fallback needed by", sum(f for _, f in flags), flush=True)
     else:
-        wl, n, seed, envs = SETS[name]
+        wl, n, seed, envs = SETS[base]
         _BATCH = scenes.make(wl, n, seed=seed)
+    _F32 = name.endswith("_f32in")
+    if _F32:
+        round_to_f32(_BATCH)
     with Pool(min(8, len(envs))) as p:
         res = p.map(_one, envs)
-    out = dict(envs=np.array(envs), workload=wl, n_env=n, seed=seed)
+    out = dict(envs=np.array(envs), workload=wl, n_env=n, seed=seed, f32_inputs=name.endswith("_f32in"))
     ragged = len({r["jac"].shape for r in res}) > 1 or len({r["G"].shape for r in res}) > 1
     out["ragged"] = ragged
     for key in ("vnext", "JtLam", "modes", "jac", "G", "g", "mu", "J"):
@@ -158,7 +247,7 @@ def make(name):
                 out[f"{key}__{i}"] = np.asarray(r[key])
         else:
             out[key] = np.array([r[key] for r in res])
-    for key in ("margin", "ok", "unique", "residual", "fallback"):
+    for key in ("margin", "ok", "unique", "residual", "fallback", "sens"):
         out[key] = np.array([r[key] for r in res])
     path = os.path.join(HERE, f"{name}.npz")
     np.savez_compressed(path, **out)
@@ -200,7 +289,12 @@ def make_rollout(name):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(SETS) + list(HARD) + list(ROLLOUTS) + list(PARAMS)):
+    default = list(SETS) + list(HARD) + [f"{x}_f32in" for x in list(SETS) + list(HARD)] + list(ROLLOUTS) + list(PARAMS)
+    if sys.argv[1:2] == ["--sensitivity"]:
+        for name in sys.argv[2:] or [f"{x}_f32in" for x in list(SETS) + list(HARD)]:
+            refresh_sensitivity(name)
+        sys.exit(0)
+    for name in (sys.argv[1:] or default):
         if name in ROLLOUTS:
             make_rollout(name)
         elif name in PARAMS:

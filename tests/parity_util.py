@@ -14,6 +14,14 @@ Per environment the comparison covers:
     averaged out, hence the factor);
   * the contact modes, exactly.
 
+In the FP32 form every tolerance is at least K times the environment's
+sensitivity `sens` stored with the FP32-input references: how far the
+oracle's own v+ moves when the contact problem's assembly (M, J, v_f) is
+perturbed by float32 rounding.  Forward error is bounded by condition times
+backward error; an ill-conditioned contact problem (a Delassus operator with
+a near-null direction) has an FP32 forward error no FP32 assembly avoids.
+Environments whose tolerance this raises are counted ("conditioned").
+
 Categories (every environment falls in one; all are counted and printed):
   gated     the oracle solved the NCP, its v+ derivative is unique, its mode
             margin is at least `margin`, the GPU reports no solver failure
@@ -43,21 +51,28 @@ GOLDEN = os.path.join(ROOT, "tests", "golden")
 # FP64 form: 1e-10; FP32 form: 1e-4.  `u` is the unit roundoff of the form's
 # working precision, `C` the constant of the near-switch tolerance (measured:
 # see the design doc, the error-versus-margin figures of the parity runs).
-TOL = {0: dict(v=1e-10, jac=1e-10, jtl=1e-10, margin=1e-6, floor=1e-11, u=1.1e-16, C=100.0, ncp=1e-8),
-       1: dict(v=1e-4, jac=1e-4, jtl=1e-4, margin=1e-3, floor=1e-6, u=6.0e-8, C=100.0, ncp=1e-4)}
+TOL = {0: dict(v=1e-10, jac=1e-10, jtl=1e-10, margin=1e-6, floor=1e-11, u=1.1e-16, C=100.0, ncp=1e-8, K=0.0),
+       1: dict(v=1e-4, jac=1e-4, jtl=1e-4, margin=1e-3, floor=1e-6, u=6.0e-8, C=100.0, ncp=1e-4, K=10.0)}
 
 
-def scaled(tol, key, margin):
-    """The tolerance of quantity `key` for an environment at this margin."""
-    if margin >= tol["margin"]:
-        return tol[key]
-    return tol[key] + tol["C"] * tol["u"] / max(margin, 1e-300)
+def scaled(tol, key, margin, sens=0.0):
+    """The tolerance of quantity `key` for an environment at this margin and
+    FP32 sensitivity."""
+    base = tol[key] if margin >= tol["margin"] else tol[key] + tol["C"] * tol["u"] / max(margin, 1e-300)
+    return max(base, tol["K"] * sens)
 
 
 def ncp_valid(G, g, mu, lam, tol):
     """Every NCP condition (Section II.B) at lam for the oracle's data."""
     from oracle import ncp
     return bool(ncp.check(np.asarray(G), np.asarray(g), np.asarray(mu), lam, tol=tol))
+
+
+def golden_for(name, precision):
+    """The stored oracle results a form is compared with: for the FP32 form
+    those computed from its float32-rounded inputs (so that the comparison
+    measures its arithmetic, not the rounding of its inputs)."""
+    return load_golden(name + "_f32in" if precision == 1 else name)
 
 
 def load_golden(name):
@@ -126,6 +141,7 @@ def compare(batch, gold, out, db, precision, envs=None, label=""):
                 ee.append(np.abs(A - B).max() / max(np.abs(B).max(), 1e-8))
         st = int(status[e])
         margin = float(gold["margin"][gi])
+        sens = float(gold["sens"][gi]) if "sens" in gold else 0.0
         mode_ok = bool(np.array_equal(modes[c0:c1].astype(np.int8), gold["modes"][gi].astype(np.int8)))
         solver_ok = not (st & (dsim.ST_NCP_NOT_CONVERGED | dsim.ST_POLISH_FAILED))
         oracle_ok = bool(gold["ok"][gi])
@@ -135,7 +151,7 @@ def compare(batch, gold, out, db, precision, envs=None, label=""):
             cat = "oracle"
         elif not solver_ok:
             cat = "flagged"
-        elif not mode_ok or ev > scaled(tol, "v", margin):
+        elif not mode_ok or ev > scaled(tol, "v", margin, sens):
             # several NCP solutions: a GPU solution that differs from the
             # oracle's must satisfy every NCP condition for the oracle's data
             cat = "alt"
@@ -146,15 +162,17 @@ def compare(batch, gold, out, db, precision, envs=None, label=""):
             cat = "near"
         else:
             cat = "gated"
-        lim = scaled(tol, "jac", margin)
-        ok = (ev <= scaled(tol, "v", margin) and ejtl <= scaled(tol, "jtl", margin)
+        lim = scaled(tol, "jac", margin, sens)
+        ok = (ev <= scaled(tol, "v", margin, sens) and ejtl <= scaled(tol, "jtl", margin, sens)
               and (not ej or (max(ej) <= lim and max(ee) <= 2 * lim)))
         rows.append(dict(env=e, ev=ev, ej=ej, ee=ee, ejtl=ejtl, status=st, mode_ok=mode_ok, cat=cat,
-                         margin=margin, ok=ok, alt_valid=alt_valid,
+                         margin=margin, ok=ok, alt_valid=alt_valid, sens=sens,
+                         conditioned=tol["K"] * sens > scaled(tol, "jac", margin),
                          fallback=bool(gold["fallback"][gi]) if "fallback" in gold else False))
     by = {c: [r for r in rows if r["cat"] == c] for c in ("gated", "near", "unpinned", "alt", "flagged", "oracle")}
     inc = by["gated"] + by["near"]
     stats = dict(n=len(rows), gated=len(by["gated"]), near=len(by["near"]), included=len(inc),
+                 conditioned=sum(r["conditioned"] for r in inc),
                  unpinned=len(by["unpinned"]), alternatives=len(by["alt"]),
                  alternatives_invalid=sum(not r["alt_valid"] for r in by["alt"]),
                  solver_flags=len(by["flagged"]), oracle_failed=len(by["oracle"]),
@@ -166,14 +184,15 @@ def compare(batch, gold, out, db, precision, envs=None, label=""):
                  jac_median=float(np.median([max(r["ej"]) for r in by["gated"] if r["ej"]]))
                  if any(r["ej"] for r in by["gated"]) else 0.0,
                  modes_agree=sum(r["mode_ok"] for r in inc), rows=rows)
-    say(f"[{label}] envs {stats['n']} gated {stats['gated']} near-switch {stats['near']} unpinned "
+    say(f"[{label}] envs {stats['n']} gated {stats['gated']} near-switch {stats['near']} "
+        f"conditioned {stats['conditioned']} unpinned "
         f"{stats['unpinned']} other valid NCP solutions {stats['alternatives'] - stats['alternatives_invalid']} "
         f"(invalid {stats['alternatives_invalid']}) solver flags {stats['solver_flags']} oracle failed "
         f"{stats['oracle_failed']} | gated: v+ max {stats['v_max']:.2e} J^T Lam max {stats['jtl_max']:.2e} "
         f"jac max {stats['jac_max']:.2e} (elementwise {stats['elem_max']:.2e}) median {stats['jac_median']:.2e} "
         f"| failures {len(stats['failures'])}")
-    for r in by["near"] + by["unpinned"] + by["alt"]:
-        say(f"    env {r['env']} {r['cat']} margin {r['margin']:.1e} v+ {r['ev']:.1e} J^T Lam {r['ejtl']:.1e} "
+    for r in by["near"] + [r for r in by["gated"] if r["conditioned"]] + by["unpinned"] + by["alt"]:
+        say(f"    env {r['env']} {r['cat']} margin {r['margin']:.1e} sensitivity {r['sens']:.1e} v+ {r['ev']:.1e} J^T Lam {r['ejtl']:.1e} "
             f"jac {max(r['ej']) if r['ej'] else 0:.1e} elementwise {max(r['ee']) if r['ee'] else 0:.1e} "
             f"modes agree {r['mode_ok']} status {r['status']}")
     for r in stats["failures"]:

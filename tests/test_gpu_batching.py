@@ -5,14 +5,14 @@ import numpy as np
 import pytest
 
 from paper_2409_07107_amd import scenes
-from tests.parity_util import TOL, assert_parity, compare, load_golden, say
+from tests.parity_util import TOL, assert_parity, compare, golden_for, say
 
 pytestmark = pytest.mark.gpu
 
 
 def _mixed(n=None, precision=1):
     from paper_2409_07107_amd import dsim
-    gold = load_golden("mixed_8192_sample")
+    gold = golden_for("mixed_8192_sample", precision)
     batch = scenes.make("mixed", n or int(gold["n_env"]), seed=int(gold["seed"]))
     return gold, batch, dsim.DeviceBatch(batch, precision=precision)
 

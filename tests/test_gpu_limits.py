@@ -34,10 +34,59 @@ def _box21(v):
     return scenes.assemble([rec])
 
 
+def _check(batch, db, out, r, precision, label, jac=None):
+    """Every output of environment 0 against the oracle's forward result `r`
+    (and, when given, its Jacobian `jac`): v+ and J^T Lam always (both
+unique for every NCP solution), the
+    impulses against every NCP condition for the oracle's (G, g, mu), and the
+    Jacobian where the modes agree at a margin above the floor, with the
+    near-switch tolerance below `margin` (at a margin below the floor the
+    one-sided derivatives differ and the Jacobian is reported only).  A solver
+    flag does not skip any of these checks."""
+    from paper_2409_07107_amd import dsim
+    from tests.parity_util import ncp_valid, scaled, _impulse_scale
+    tol = TOL[precision]
+    assert r["info"]["ok"], "the oracle did not solve this case"
+    st = int(out["status"][0])
+    vn = out["v_next"].double().cpu().numpy()
+    assert np.isfinite(vn).all()
+    scale = max(np.abs(r["vnext"]).max(), np.abs(batch.v).max(), 9.81 * batch.dt)
+    ev = np.abs(vn - r["vnext"]).max() / scale
+    nc = len(r["modes"])
+    lam = out["lam"][:3 * nc].double().cpu().numpy()
+    s = max(np.abs(r["JtLam"]).max(), _impulse_scale(r["G"], r["g"], r["J"]), 1e-300)
+    ejtl = np.abs(r["J"].T @ lam - r["JtLam"]).max() / s
+    modes = out["mode"][:nc].cpu().numpy()
+    agree = bool(np.array_equal(modes, np.array(r["modes"])))
+    margin = float(r["margin"])
+    valid = ncp_valid(r["G"], r["g"], r["model"].mu, lam, tol["ncp"])
+    say(f"{label}: status {st}, v+ {ev:.2e}, "
+        f"J^T Lam {ejtl:.2e}, NCP conditions {'hold' if valid else 'VIOLATED'}, modes agree {agree}, "
+        f"oracle margin {margin:.1e}")
+    assert valid
+    assert ev <= tol["v"]
+    assert ejtl <= tol["jtl"]
+    if jac is None:
+        return
+    n = batch.max_sizes[1]
+    J = dsim.split_jacobian(db, out, 0)
+    assert np.isfinite(J).all()
+    err = [np.linalg.norm(J[:, n * k:n * k + n] - jac[:, n * k:n * k + n]) /
+           max(np.linalg.norm(jac[:, n * k:n * k + n]), 1e-8) for k in range(3)]
+    gated = agree and margin >= tol["floor"]
+    say(f"  Jacobian blocks dq, dv, dtau: relative errors {', '.join(f'{x:.2e}' for x in err)} "
+        f"({'gated' if gated else 'reported: ' + ('modes differ, another valid NCP solution' if not agree else 'contact at a switching surface')})")
+    if gated:
+        lim = scaled(tol, "jac", margin)
+        for k in range(3):
+            assert err[k] <= lim, k
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_largest_tree(precision, gpu_lib):
     import torch
     from paper_2409_07107_amd import dsim
+    from oracle import derivative
     from oracle.step import forward
     batch = _chain()
     assert batch.max_sizes[1] == 64
@@ -45,85 +94,37 @@ def test_largest_tree(precision, gpu_lib):
     out = dsim.step(db)
     torch.cuda.synchronize()
     r = forward(batch.env(0))
-    st = int(out["status"][0])
-    say(f"64-dof chain: status {st}, oracle modes {r['modes']}")
-    if not st & 17 and r["info"]["ok"]:
-        v = out["v_next"].double().cpu().numpy()
-        scale = max(np.abs(r["vnext"]).max(), np.abs(batch.v).max(), 9.81 * batch.dt)
-        assert np.abs(v - r["vnext"]).max() / scale <= TOL[precision]["v"]
+    _check(batch, db, out, r, precision, "64-dof chain, step")
     if precision == dsim.F64:
         with pytest.raises(dsim.DsimError, match="-2"):
             dsim.step_jacobian(db)
         return
-    from oracle import derivative
     out = dsim.step_jacobian(db)
     torch.cuda.synchronize()
-    st = int(out["status"][0])
-    modes = out["mode"][:4].cpu().numpy()
-    assert np.isfinite(dsim.split_jacobian(db, out, 0)).all()
-    if st & 17 or not r["info"]["ok"] or not np.array_equal(modes, np.array(r["modes"])):
-        say(f"  status {st}, modes {modes.tolist()}: Jacobian not compared")
-        return
     d = derivative.ift(batch.env(0), r)
-    J = dsim.split_jacobian(db, out, 0)
-    n = 64
-    for k in range(3):
-        A, B = J[:, n * k:n * k + n], d["jac"][:, n * k:n * k + n]
-        err = np.linalg.norm(A - B) / max(np.linalg.norm(B), 1e-8)
-        say(f"  block {k}: relative error {err:.2e}")
-        assert err <= TOL[precision]["jac"], k
+    _check(batch, db, out, r, precision, "64-dof chain, Jacobian", jac=d["jac"])
 
 
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("v", [[0.0, 0.0, -0.05, 0.0, 0.0, 0.0], [0.4, -0.2, -0.05, 0.0, 0.0, 0.0]])
 def test_most_contacts(precision, v, gpu_lib):
     """21 coplanar contacts under one box: the impulses are statically
-    indeterminate (rank 6), v+ is unique.  The step is compared on v+; the
-    Jacobian is compared where the modes agree with the oracle's, and
-    otherwise the GPU impulses must solve the oracle's NCP (a different,
-    valid distribution of the load)."""
+    indeterminate (rank 6) and v+ is unique.  The load distribution leaves
+    contacts with zero impulse and zero normal velocity (margin 0), so the
+    Jacobian is reported and v+, J^T Lam and the NCP conditions are gated."""
     import torch
     from paper_2409_07107_amd import dsim
     from oracle import derivative
     from oracle.step import forward
-    from tests.parity_util import ncp_valid
     batch = _box21(np.array(v))
     assert batch.max_sizes[3] == 21
     db = dsim.DeviceBatch(batch, precision=precision)
     env = batch.env(0)
     r = forward(env)
-    tol = TOL[precision]
-    scale = max(np.abs(r["vnext"]).max(), np.abs(batch.v).max(), 9.81 * batch.dt)
     out = dsim.step(db)
     torch.cuda.synchronize()
-    st = int(out["status"][0])
-    vn = out["v_next"].double().cpu().numpy()
-    say(f"box with 21 contacts, precision {precision}: status {st}, oracle modes {sorted(set(r['modes']))}")
-    assert np.isfinite(vn).all()
-    if not st & 17:
-        assert np.abs(vn - r["vnext"]).max() / scale <= tol["v"]
+    _check(batch, db, out, r, precision, f"box with 21 contacts, v {v[:3]}, step")
     out = dsim.step_jacobian(db)
     torch.cuda.synchronize()
-    st = int(out["status"][0])
-    if st & 17:
-        say("  solver flagged: Jacobian not compared")
-        return
-    modes = out["mode"][:21].cpu().numpy()
-    if np.array_equal(modes, np.array(r["modes"])):
-        d = derivative.ift(env, r)
-        J = dsim.split_jacobian(db, out, 0)
-        err = [np.linalg.norm(J[:, 6 * k:6 * k + 6] - d["jac"][:, 6 * k:6 * k + 6]) /
-               max(np.linalg.norm(d["jac"][:, 6 * k:6 * k + 6]), 1e-8) for k in range(3)]
-        say(f"  modes agree: Jacobian relative errors {', '.join(f'{x:.2e}' for x in err)}")
-        assert np.isfinite(J).all()
-        if st & dsim.ST_MODE_DEGENERATE:
-            # a contact within mode_eps of a mode switch: the one-sided
-            # derivatives differ there, so the comparison is reported only
-            say("  a contact at a mode boundary: reported, not gated")
-            return
-        for k in range(3):
-            assert err[k] <= tol["jac"], k
-    else:
-        lam = out["lam"][:63].double().cpu().numpy()
-        assert ncp_valid(r["G"], r["g"], r["model"].mu, lam, tol["ncp"])
-        say("  another valid distribution of the impulses: NCP conditions checked")
+    _check(batch, db, out, r, precision, f"box with 21 contacts, v {v[:3]}, Jacobian",
+           jac=derivative.ift(env, r)["jac"])

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07107_amd import scenes
-from tests.parity_util import TOL, assert_parity, compare, load_golden, say
+from tests.parity_util import TOL, assert_parity, compare, golden_for, say
 
 pytestmark = pytest.mark.gpu
 
@@ -14,7 +14,7 @@ CASES = [("cube8", 0), ("cube8", 1), ("arm7_64", 0), ("arm7_64", 1), ("tree36_24
 def _run(name, precision, threads=0):
     import torch
     from paper_2409_07107_amd import dsim
-    gold = load_golden(name)
+    gold = golden_for(name, precision)
     batch = scenes.make(str(gold["workload"]), int(gold["n_env"]), seed=int(gold["seed"]))
     db = dsim.DeviceBatch(batch, precision=precision)
     p = db.params(threads=threads)

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07107_amd import scenes
-from tests.parity_util import TOL, assert_parity, compare, load_golden, say
+from tests.parity_util import TOL, assert_parity, compare, golden_for, say
 
 pytestmark = pytest.mark.gpu
 
@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 def _run(name, precision):
     import torch
     from paper_2409_07107_amd import dsim
-    gold = load_golden(name)
+    gold = golden_for(name, precision)
     batch = scenes.make(str(gold["workload"]), int(gold["n_env"]), seed=int(gold["seed"]))
     db = dsim.DeviceBatch(batch, precision=precision)
     say(f"run {name} precision {precision} n_env {batch.n_env}")

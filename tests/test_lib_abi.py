@@ -133,14 +133,15 @@ def test_short_workspace_is_rejected_before_any_launch(L):
     for prec in (dsim.F32, dsim.F64):
         p = dsim.params(prec)
         need = L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_JACOBIAN)
-        assert need > 504 * b.n_env
+        slot = 8 * dsim.WS_ENV_DOUBLES  # impulses and solver counts per environment
+        assert need > slot * b.n_env
         assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), None, need, None) == -4
         assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy, need - 1,
                                     None) == -4
         # a workspace sized for the impulses alone is too short: the step's
         # hand-over records follow them
         assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy,
-                                    504 * b.n_env, None) == -4
+                                    slot * b.n_env, None) == -4
 
 
 def test_on_chip_sizing(L):
@@ -156,9 +157,10 @@ def test_on_chip_sizing(L):
         # (FP32) or three (FP64) teams on one compute unit
         step = L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_STEP)
         assert step <= 160 * 1024 // (4 if prec == dsim.F32 else 3)
-        # the derivative entries hand 63 FP64 impulses per environment over
-        # from their step launch, then one record of the step's quantities
-        # per environment; the step entries need no workspace
+        # the derivative entries hand 63 FP64 impulses and the solver's
+        # counts (DSIM_WS_ENV_DOUBLES doubles) per environment over from their
+        # step launch, then one record of the step's quantities per
+        # environment; the step entries need no workspace
         NB, NV, NQ, NC = b.max_sizes
         K = 3 * NC
         r = 4 if prec == dsim.F32 else 8
@@ -166,7 +168,7 @@ def test_on_chip_sizing(L):
         doubles = [9 * NB, 3 * NB, 6 * NV, 6 * NB, 10 * NB, 10 * NB, 3 * NC, NV * NV, K, 3 * K, 3 * K, K, 4 * NC,
                    K * K, NV, NV]
         record = sum(pad(8 * x) for x in doubles) + 2 * pad(r * K * NV) + 4 * pad(4 * K) + pad(16)
-        expect = (b.n_env * 63 + 1) // 2 * 2 * 8 + b.n_env * record
+        expect = (b.n_env * dsim.WS_ENV_DOUBLES + 1) // 2 * 2 * 8 + b.n_env * record
         for entry in (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP, dsim.ENTRY_STEP_INTEGRATE_VJP, dsim.ENTRY_VJP_PARAMS,
                       dsim.ENTRY_JACOBIAN_PARAMS):
             assert L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), entry) == expect
