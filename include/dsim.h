@@ -296,6 +296,29 @@ int32_t dsim_vjp_kept(const dsim_batch* batch, const dsim_params* params,
                       void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * dsim_step_vjp without a caller workspace and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Arguments, outputs
+ * and results are those of dsim_step_vjp; the hand-over between its launches
+ * lives in a static device array of dsim_noalloc_scratch_bytes() bytes
+ * (64 MiB: about 1800 environments of 31 bodies, 36 dofs and 8 contacts in
+ * FP32) that each GPU the library runs on holds until the process ends.  A
+ * batch whose hand-over (dsim_workspace_bytes for DSIM_ENTRY_VJP) exceeds it
+ * is rejected with DSIM_ERR_WORKSPACE before any device call; DSIM_ERR_DEVICE
+ * if the array's address cannot be obtained on the current device.  Every
+ * call on a GPU shares that GPU's array, so calls that overlap on one GPU
+ * (for instance on two streams) race; calls in stream order do not.
+ */
+int32_t dsim_step_vjp_noalloc(const dsim_batch* batch, const dsim_params* params,
+                              const void* q, const void* v, const void* tau,
+                              const void* g_vnext, const void* g_lam,
+                              void* v_next, void* lam, int8_t* mode, int32_t* status,
+                              void* g_q, void* g_v, void* g_tau, void* stream);
+
+/* Bytes of the static workspace of dsim_step_vjp_noalloc. */
+size_t dsim_noalloc_scratch_bytes(void);
+
+/*
  * Reverse mode in the physical parameters as well (derivatives with respect
  * to physical parameters, Section II.D, by the implicit differentiation of
  * the same mode system): everything dsim_step_vjp computes (g_lam as

@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/dsim.h"
 #include "dsim_pipeline.h"
@@ -15,6 +16,14 @@ using namespace dsim;
 
 static_assert(kLdStride == DSIM_WS_ENV_DOUBLES && kLdWork == DSIM_WS_WORK,
               "the documented layout of the impulse hand-over");
+
+// The workspace of dsim_step_vjp_noalloc: a file-scope device array that
+// every GPU the library runs on holds until the process ends.  In host code
+// its name is only a stand-in for the symbol: the device address comes from
+// hipGetSymbolAddress, once per device (with that device current), and is
+// the only form host code hands to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -331,9 +340,47 @@ int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const voi
                                  ws, ws_bytes, stream);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (set up on the first call on
+// that device), or nullptr if the device or the symbol is not available.
+void* scratch_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t dsim_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int32_t dsim_step_vjp_noalloc(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                              const void* tau, const void* g_vnext, const void* g_lam, void* v_next, void* lam,
+                              int8_t* mode, int32_t* status, void* g_q, void* g_v, void* g_tau, void* stream) {
+    if (!g_vnext || !g_q || !g_v || !g_tau) return DSIM_ERR_ARG;
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    // the batch's hand-over must fit the static workspace; checked before
+    // any device call
+    if (handover_bytes(b, p) > kScratchBytes) return DSIM_ERR_WORKSPACE;
+    void* ws = scratch_address();
+    if (!ws) return DSIM_ERR_DEVICE;
+    // the step launches write every hand-over record the derivative launch
+    // reads, so nothing in the array needs clearing between calls
+    return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, g_lam, v_next, lam, mode, status, g_q, g_v, g_tau,
+                               nullptr, nullptr, ws, kScratchBytes, stream);
+}
 
 void dsim_default_params(dsim_params* p, int32_t precision) {
     if (!p) return;

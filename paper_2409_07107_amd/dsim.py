@@ -29,7 +29,7 @@ SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
            "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params",
            "dsim_step_jacobian_params", "dsim_ambient_to_tangent", "dsim_status_string",
-           "dsim_step_keep", "dsim_vjp_kept")
+           "dsim_step_keep", "dsim_vjp_kept", "dsim_step_vjp_noalloc", "dsim_noalloc_scratch_bytes")
 
 _vp = ctypes.c_void_p
 
@@ -92,6 +92,10 @@ def lib():
         L.dsim_vjp_kept.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 10 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_vjp_kept.restype = ctypes.c_int32
+        L.dsim_step_vjp_noalloc.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13
+        L.dsim_step_vjp_noalloc.restype = ctypes.c_int32
+        L.dsim_noalloc_scratch_bytes.argtypes = []
+        L.dsim_noalloc_scratch_bytes.restype = ctypes.c_size_t
         L.dsim_step_vjp_params.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_step_vjp_params.restype = ctypes.c_int32
@@ -400,6 +404,27 @@ def step_vjp(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | No
                                _ptr(g_vnext), _ptr(g_lam), _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]),
                                _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]), _ptr(out["g_tau"]),
                                _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_vjp_noalloc(db: DeviceBatch, g_vnext, q=None, v=None, tau=None, p: CParams | None = None, out=None,
+                     cb=None, g_lam=None):
+    """step_vjp through dsim_step_vjp_noalloc: the same outputs, with the
+    library's static workspace instead of one allocated here (the output
+    tensors are the caller's: pass `out` to allocate nothing at all)."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    if out is None:
+        out = _outputs(db)
+        for k in ("g_q", "g_v", "g_tau"):
+            out[k] = torch.empty(db.n_dof, dtype=db.dtype, device=db.device)
+    _check(lib().dsim_step_vjp_noalloc(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v),
+                                       _ptr(tau), _ptr(g_vnext), _ptr(g_lam), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                       _ptr(out["mode"]), _ptr(out["status"]), _ptr(out["g_q"]), _ptr(out["g_v"]),
+                                       _ptr(out["g_tau"]), ctypes.c_void_p(_stream())))
     return out
 
 

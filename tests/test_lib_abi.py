@@ -178,3 +178,24 @@ def test_on_chip_sizing(L):
         assert L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_JACOBIAN_PARAMS) == lds
         assert L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_VJP_PARAMS) == \
             L.dsim_lds_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_VJP)
+
+
+def test_noalloc_entry_rejects_batches_beyond_its_static_workspace(L):
+    """dsim_step_vjp_noalloc refuses a batch whose hand-over does not fit its
+    static workspace, with DSIM_ERR_WORKSPACE and before any device call (the
+    array pointers below are never dereferenced)."""
+    from paper_2409_07107_amd import dsim
+    keep = []
+    batch = scenes.make("tree36", 2048, seed=1)
+    cb = dsim._host_batch_struct(batch, keep)
+    p = dsim.params(dsim.F32)
+    need = L.dsim_workspace_bytes(ctypes.byref(cb), ctypes.byref(p), dsim.ENTRY_VJP)
+    assert L.dsim_noalloc_scratch_bytes() == 64 << 20
+    assert need > L.dsim_noalloc_scratch_bytes()
+    dummy = ctypes.c_void_p(16)
+    rc = L.dsim_step_vjp_noalloc(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 12), None)
+    assert rc == -4 and L.dsim_error_string(rc) == b"workspace too small"
+    # a null output is an argument error, found before the size check
+    args = [dummy] * 12
+    args[9] = None
+    assert L.dsim_step_vjp_noalloc(ctypes.byref(cb), ctypes.byref(p), *args, None) == -1
