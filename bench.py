@@ -47,21 +47,26 @@ WORKLOADS = {
 }
 KERNEL = "env_kernel<float, jacobian>"
 STEP_KERNEL = "env_kernel<float, step>"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "env_kernel_f32_step_tree36_16384_traffic.json")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f"env_kernel_f32_step_{x}_pass_tree36_16384_traffic.json")
+                 for x in ("first", "fallback")]
 
 
 def measured_traffic():
-    """HBM bytes per launch of the timed kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel
-    calibration), or None when absent or taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    with open(TRAFFIC_FILE) as fh:
-        t = json.load(fh)
+    """HBM bytes of the step's two launches (first pass + fallback pass) of
+    a dsim_step_jacobian call, from the committed counter summaries
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration),
+    or None when absent or taken on other kernel sources."""
     from paper_2409_07107_amd.profiling import source_digest
-    if t.get("source_sha1") != source_digest():
-        return None
-    return float(t["bytes_per_launch"])
+    total = 0.0
+    for f in TRAFFIC_FILES:
+        if not os.path.exists(f):
+            return None
+        with open(f) as fh:
+            t = json.load(fh)
+        if t.get("source_sha1") != source_digest():
+            return None
+        total += float(t["bytes_per_launch"])
+    return total
 
 
 def algorithmic_flops(batch, modes, sweeps, work=None):
