@@ -74,4 +74,5 @@ class HostLib:
                                   int(e0), int(e1), int(bool(region_alloc)))
         if rc != 0:
             raise RuntimeError(f"host run failed: {rc}")
+        out["ws"] = ws
         return out
