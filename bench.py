@@ -395,7 +395,9 @@ def run_rollout(args):
         "config": {"workload": "tree36 x 1024, 200 steps, torques N(0, 0.5^2), base-position loss; forward + "
                                "recompute + reverse per rollout", "n_env": n, "steps": T, "checkpoint": C,
                    "seed": 0},
-        "launches_per_rollout": T + (T - T // C) + 2 * T,
+        # two step launches (first pass, fallback pass) per forward and
+        # recomputed step, three per reverse step (the two, then the adjoint)
+        "launches_per_rollout": 2 * T + 2 * (T - T // C) + 3 * T,
         "flagged_envs": int(((status & 17) != 0).sum()),
         "finite_gradients": bool(torch.isfinite(grad).all()),
     }
