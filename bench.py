@@ -396,8 +396,9 @@ def run_rollout(args):
                                "recompute + reverse per rollout", "n_env": n, "steps": T, "checkpoint": C,
                    "seed": 0},
         # two step launches (first pass, fallback pass) per forward and
-        # recomputed step, three per reverse step (the two, then the adjoint)
-        "launches_per_rollout": 2 * T + 2 * (T - T // C) + 3 * T,
+        # recomputed step, four per reverse step (the two, then the adjoint
+        # of the environments the first pass solved and of the others)
+        "launches_per_rollout": 2 * T + 2 * (T - T // C) + 4 * T,
         "flagged_envs": int(((status & 17) != 0).sum()),
         "finite_gradients": bool(torch.isfinite(grad).all()),
     }

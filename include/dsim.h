@@ -29,7 +29,11 @@
  * params->precision == DSIM_F32 and double when DSIM_F64; index arrays are
  * int32.  Buffers must stay valid until the work on `stream` has completed.
  * `stream` is a hipStream_t (NULL = the default stream); all compute calls are
- * asynchronous on it.
+ * asynchronous on it.  The derivative entries (outside graph capture, and
+ * except dsim_step_vjp_noalloc) run part of their work on a second stream
+ * that the library creates once per device (default priority), forked from
+ * and joined back to `stream` with events: the call's work is complete, and
+ * its outputs ready, in `stream`'s order as for any other call.
  *
  * Errors: every call returns 0 (DSIM_SUCCESS) or a negative DSIM_ERR_* code
  * for invalid arguments, unsupported sizes or a failed launch; these are the
@@ -195,8 +199,8 @@ int32_t dsim_validate_params(const dsim_params* params);
 
 /* Bytes of device workspace the given entry needs for this batch: 0 for the
  * step entries; for the derivative entries (Jacobian, VJP, parameter
- * gradients and the rollout adjoint), which run as two launches on `stream`
- * -- the step, then the derivative -- the hand-over between them: each
+ * gradients and the rollout adjoint), which run the step launches, then the
+ * derivative launches, the hand-over between them: each
  * environment's FP64 contact impulses and solver counts (DSIM_WS_ENV_DOUBLES doubles,
  * at the start of the workspace) and a record of the step's
  * quantities that the derivative reads (kinematics, inertias, M^-1, the
@@ -211,7 +215,8 @@ size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, 
  * FP64 contact impulses (3 n_c), then, from index DSIM_WS_WORK, the work its
  * contact solve executed in the call: Gauss-Seidel sweeps of the first pass,
  * Levenberg-Marquardt iterations and damped linear solves, and ADMM
- * iterations of the fallback pass (Section II.B solvers), as doubles.  Valid
+ * iterations of the fallback pass (Section II.B solvers), then 1 if the first
+ * pass left the environment to the fallback pass, else 0; as doubles.  Valid
  * after the call completes, until the workspace is reused. */
 #define DSIM_WS_ENV_DOUBLES 68
 #define DSIM_WS_WORK 63

@@ -132,6 +132,13 @@ __global__ __launch_bounds__(512) void env_kernel(BatchView<R> B, Params P, Dims
     // the fallback pass of the solve recomputes only the environments the
     // first pass left unsolved (the whole workgroup exits for the others)
     if (P.pass == 1 && !(status[e] & (ST_NCP | ST_POLISH))) return;
+    // a derivative launch split in two: pass 2 differentiates the
+    // environments the first step pass solved (while the fallback pass runs
+    // on the others), pass 3 the others, after the fallback pass
+    if (P.pass >= 2 && ld) {
+        const bool fb = ld[size_t(e) * kLdStride + kLdFallback] != 0.0;
+        if (fb != (P.pass == 3)) return;
+    }
     Env<R> E;
     carve<R>(smem, D, ENTRY, E);
     run_env<R>(T, E, B, P, D, ENTRY, e, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld);
@@ -268,6 +275,50 @@ size_t handover_bytes(const dsim_batch* b, const dsim_params* p) {
     return imp + size_t(b->n_env) * rec;
 }
 
+constexpr int kMaxDevices = 64;
+
+// Per device, a second stream (default priority) and two events with which a
+// derivative entry runs its fallback pass beside the derivative launch of
+// the environments the first pass solved; created on first use.  The
+// enqueue sequence that uses them is serialised by `mutex`, so concurrent
+// callers may share them.  A call on a stream under graph capture does not
+// use them: its launches stay on the caller's stream in order (a fork of
+// the capture onto this shared stream made the runtime crash when the
+// capture ended).
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool failed = false;
+    std::mutex mutex;
+};
+SideStream g_side[kMaxDevices];
+std::mutex g_side_setup;
+
+SideStream* side_stream(hipStream_t caller) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(caller, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    SideStream& ss = g_side[dev];
+    std::lock_guard<std::mutex> lock(g_side_setup);
+    if (ss.stream) return &ss;
+    if (ss.failed) return nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+        if (st) (void)hipStreamDestroy(st);
+        if (a) (void)hipEventDestroy(a);
+        ss.failed = true;
+        return nullptr;
+    }
+    ss.stream = st;
+    ss.fork = a;
+    ss.join = b;
+    return &ss;
+}
+
 // The step is two launches of the step kernel on the same stream: the first
 // pass of the solve over every environment, then its fallback pass, whose
 // workgroups exit at once for the environments the first pass solved (its
@@ -281,7 +332,7 @@ size_t handover_bytes(const dsim_batch* b, const dsim_params* p) {
 template <class R, int ENTRY>
 int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
            const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
-           void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream) {
+           void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream, bool fork) {
     if (b->n_env == 0) return DSIM_SUCCESS;
     if (!entry_has_derivative(ENTRY)) {
         int rc = launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
@@ -293,13 +344,36 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
     if (!ws || ws_bytes < handover_bytes(b, p)) return DSIM_ERR_WORKSPACE;
     if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
     double* ld = static_cast<double*>(ws);
-    for (int pass = 0; pass < 2; ++pass) {
-        int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
-                                           nullptr, nullptr, nullptr, nullptr, ld, stream, pass);
+    int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                       nullptr, nullptr, nullptr, nullptr, ld, stream, 0);
+    if (rc) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    SideStream* side = fork ? side_stream(s) : nullptr;
+    if (!side) {
+        rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                       nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
         if (rc) return rc;
+        return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
+                                    ld, stream);
     }
+    // The fallback pass on the side stream, beside the derivative of the
+    // environments the first pass solved (each launch touches only its own
+    // environments' outputs and records); then the derivative of the others.
+    std::lock_guard<std::mutex> lock(side->mutex);
+    if (hipEventRecord(side->fork, s) != hipSuccess || hipStreamWaitEvent(side->stream, side->fork, 0) != hipSuccess)
+        return DSIM_ERR_LAUNCH;
+    rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, ld, side->stream, 1);
+    const bool joined = hipEventRecord(side->join, side->stream) == hipSuccess;
+    const int rc2 = launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
+                                         ld, stream, 2);
+    // the caller's stream waits for the side stream whatever failed, so that
+    // no work of this call is left outside its stream's order
+    if (!joined || hipStreamWaitEvent(s, side->join, 0) != hipSuccess) return DSIM_ERR_LAUNCH;
+    if (rc) return rc;
+    if (rc2) return rc2;
     return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5, ld,
-                                stream);
+                                stream, 3);
 }
 
 // The halves of a derivative entry as separate calls: the step launches
@@ -328,19 +402,18 @@ int launch_half(int half, const dsim_batch* b, const dsim_params* p, const void*
 template <int ENTRY>
 int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
              const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
-             void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream) {
+             void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream, bool fork = true) {
     int rc = check_common(b, p);
     if (rc) return rc;
     if (b->n_env == 0) return DSIM_SUCCESS;
     if (!q || !v || !tau || !v_next || !status || !mode || !lam) return DSIM_ERR_ARG;
     if (p->precision == DSIM_F32)
         return launch<float, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
-                                    ws, ws_bytes, stream);
+                                    ws, ws_bytes, stream, fork);
     return launch<double, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
-                                 ws, ws_bytes, stream);
+                                 ws, ws_bytes, stream, fork);
 }
 
-constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
 void* g_scratch_ptr[kMaxDevices] = {};
 
@@ -378,8 +451,9 @@ int32_t dsim_step_vjp_noalloc(const dsim_batch* b, const dsim_params* p, const v
     if (!ws) return DSIM_ERR_DEVICE;
     // the step launches write every hand-over record the derivative launch
     // reads, so nothing in the array needs clearing between calls
+    // one stream, no side stream or events: nothing is created
     return dispatch<ENTRY_VJP>(b, p, q, v, tau, g_vnext, g_lam, v_next, lam, mode, status, g_q, g_v, g_tau,
-                               nullptr, nullptr, ws, kScratchBytes, stream);
+                               nullptr, nullptr, ws, kScratchBytes, stream, false);
 }
 
 void dsim_default_params(dsim_params* p, int32_t precision) {

@@ -164,6 +164,8 @@ enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP 
 // sweeps of the first pass, Levenberg-Marquardt iterations and linear
 // solves and ADMM iterations of the fallback pass
 constexpr int kLdWork = 63;
+// then whether the first pass left the environment unsolved (1) or not (0)
+constexpr int kLdFallback = 67;
 constexpr int kLdStride = 68;
 
 DSIM_HD inline bool entry_has_derivative(int entry) {

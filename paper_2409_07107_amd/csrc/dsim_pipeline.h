@@ -926,7 +926,10 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
                 // executed solver work: the first pass writes its sweeps and
                 // clears the fallback's counts, the fallback pass (run only
                 // for the environments the first left unsolved) writes its own
-                if (P.pass == 0) l[kLdWork] = double(E.hdr[7]);
+                if (P.pass == 0) {
+                    l[kLdWork] = double(E.hdr[7]);
+                    l[kLdFallback] = (E.hdr[5] & (ST_NCP | ST_POLISH)) ? 1.0 : 0.0;
+                }
                 l[kLdWork + 1] = double(E.hdr[8]);
                 l[kLdWork + 2] = double(E.hdr[3]);
                 l[kLdWork + 3] = double(E.hdr[15]);

@@ -128,6 +128,18 @@ def _label(name: str, alternate: list[str] | None, seen: dict) -> str:
     return alternate[i % len(alternate)] if alternate else ""
 
 
+def _labels_for(name: str, a) -> list[str] | None:
+    """The labels dealt to this kernel's dispatches: from --alternate-spec
+    ("SUBSTR=LABEL,LABEL;..."), else --alternate with --alternate-kernel."""
+    for part in filter(None, (getattr(a, "alternate_spec", "") or "").split(";")):
+        key, labels = part.split("=", 1)
+        if key in name:
+            return labels.split(",")
+    if a.alternate and a.alternate_kernel and a.alternate_kernel in name:
+        return a.alternate.split(",")
+    return None
+
+
 def cmd_dispatches(a):
     alt = a.alternate.split(",") if a.alternate else None
     groups, seen = {}, {}
@@ -137,7 +149,7 @@ def cmd_dispatches(a):
         if a.kernel not in r["Kernel_Name"]:
             continue
         name = r["Kernel_Name"]
-        lab = _label(name, alt if (a.alternate_kernel and a.alternate_kernel in name) else None, seen)
+        lab = _label(name, _labels_for(name, a), seen)
         ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
         groups.setdefault((name, lab), []).append(ms)
     lines = [f"# rocprofv3 dispatch durations: {a.title}", "", "Command:", "", "```", a.cmd, "```", "",
@@ -168,8 +180,7 @@ def cmd_counters(a):
                 continue
             key = (d, r["Dispatch_Id"])
             if key not in lab_of:
-                lab_of[key] = _label(name, alt if (a.alternate_kernel and a.alternate_kernel in name) else None,
-                                     seen)
+                lab_of[key] = _label(name, _labels_for(name, a), seen)
             slot = per.setdefault((name, lab_of[key]), {}).setdefault(key, {})
             c, x = r["Counter_Name"], float(r["Counter_Value"])
             # SQ counters add over their instances; the GRBM clock is one per
@@ -242,6 +253,7 @@ def main():
         c.add_argument("--kernel", default="")
         c.add_argument("--alternate", default="", help="labels dealt in turn to a kernel's dispatches")
         c.add_argument("--alternate-kernel", default="", help="the kernel (substring) whose dispatches alternate")
+        c.add_argument("--alternate-spec", default="", help="SUBSTR=LABEL,LABEL;... per kernel")
         c.add_argument("--title", default="")
         c.add_argument("--cmd", required=True)
         c.add_argument("--note", default="")
