@@ -373,10 +373,8 @@ def run_rollout(args):
     n, T, C = 1024, 200, 20
     batch = scenes.make("tree36", n, seed=0)
     db = dsim.DeviceBatch(batch, precision=dsim.F32)
-    rng = np.random.default_rng(1)
-    taus = torch.as_tensor(rng.normal(scale=0.5, size=(T, db.n_dof)), dtype=db.dtype, device=db.device)
-    targets = np.stack([batch.q[batch.cfg_off[e]:batch.cfg_off[e] + 3] + rng.normal(scale=0.1, size=3)
-                        for e in range(n)])
+    tau_np, targets = scenes.rollout_inputs(batch, T, 1)
+    taus = torch.as_tensor(tau_np, dtype=db.dtype, device=db.device)
     lf = rollout.base_position_loss(db, targets)
     reps = max(1, min(args.steps, 3))
     rollout.rollout_gradient(db, db.q, db.v, taus, lf, checkpoint=C)  # warm-up
@@ -387,13 +385,27 @@ def run_rollout(args):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / reps
     status = info["status"].cpu().numpy()
+    check = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "rollout_fd_tree36_1024.npz")
+    if os.path.exists(gold_path):
+        # the gradient along the stored directions of the sampled
+        # environments against the oracle's central differences
+        from tests.parity_util import LONG_TOL, load_golden, long_rollout_check
+        gold = load_golden("rollout_fd_tree36_1024")
+        rows, counts = long_rollout_check(db, batch, tau_np, targets, [int(e) for e in gold["envs"]], gold, C)
+        cmp = [r["rel"] for r in rows if r["why"] == "compared"]
+        check = {"reference": "FP64 oracle central differences (h = 1e-6) of the whole rollout, 4 directions on "
+                              "16 sampled environments", "counts": counts, "tolerance": LONG_TOL[dsim.F32],
+                 "max_rel_error": max(cmp) if cmp else None,
+                 "median_rel_error": float(np.median(cmp)) if cmp else None,
+                 "within_tolerance": sum(x <= LONG_TOL[dsim.F32] for x in cmp)}
     line = {
         "metric": "rollout gradient env-steps/sec (36-dof tree, 8 contacts, 200 steps, checkpoint 20), FP32",
         "value": n * T / wall, "unit": "env-steps/s", "n_gpus": 1, "steps": reps, "warmup": 1,
         "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "tree36 x 1024, 200 steps, torques N(0, 0.5^2), base-position loss; forward + "
-                               "recompute + reverse per rollout", "n_env": n, "steps": T, "checkpoint": C,
+        "config": {"workload": "tree36 x 1024, 200 steps, joint torques N(0, 0.5^2), base-position loss; forward "
+                               "+ recompute + reverse per rollout", "n_env": n, "steps": T, "checkpoint": C,
                    "seed": 0},
         # two step launches (first pass, fallback pass) per forward and
         # recomputed step, four per reverse step (the two, then the adjoint
@@ -401,6 +413,7 @@ def run_rollout(args):
         "launches_per_rollout": 2 * T + 2 * (T - T // C) + 4 * T,
         "flagged_envs": int(((status & 17) != 0).sum()),
         "finite_gradients": bool(torch.isfinite(grad).all()),
+        "gradient_check": check,
     }
     print(json.dumps(line), flush=True)
 

@@ -425,6 +425,40 @@ def make(name: str, n_env: int, seed: int = 0, **kw) -> Batch:
     return WORKLOADS[name](n_env=n_env, seed=seed, **kw)
 
 
+def actuated_dofs(batch: Batch) -> np.ndarray:
+    """Mask over all dofs: True for joint dofs, False for free-flyer dofs
+    (a free flyer carries no actuator)."""
+    m = np.ones(int(batch.dof_off[-1]), dtype=bool)
+    for e in range(batch.n_env):
+        b0, b1 = batch.body_off[e], batch.body_off[e + 1]
+        d = batch.dof_off[e]
+        for b in range(b0, b1):
+            nd = 6 if int(batch.jtype[b]) == FREEFLYER else 1
+            if nd == 6:
+                m[d:d + 6] = False
+            d += nd
+    return m
+
+
+def rollout_inputs(batch: Batch, steps: int, seed: int, tau_std=0.5, target_std=0.1):
+    """Torque sequences (steps x sum n_v, N(0, tau_std^2) on joint dofs,
+    zero on free-flyer dofs) and base-position targets (n_env x 3: the
+    initial base position plus N(0, target_std^2)) for rollouts."""
+    rng = np.random.default_rng(seed)
+    taus = rng.normal(scale=tau_std, size=(steps, int(batch.dof_off[-1]))) * actuated_dofs(batch)
+    targets = np.stack([batch.q[batch.cfg_off[e]:batch.cfg_off[e] + 3] + rng.normal(scale=target_std, size=3)
+                        for e in range(batch.n_env)])
+    return taus, targets
+
+
+def rollout_directions(batch: Batch, e: int, steps: int, count: int, seed: int) -> np.ndarray:
+    """`count` random torque directions (count x steps x n_v of environment
+    e, N(0, 1) on its joint dofs, zero on free-flyer dofs)."""
+    rng = np.random.default_rng(seed)
+    d0, d1 = batch.dof_off[e], batch.dof_off[e + 1]
+    return rng.normal(size=(count, steps, d1 - d0)) * actuated_dofs(batch)[d0:d1]
+
+
 def concat(batches) -> Batch:
     """Concatenate batches that share dt, gravity and gap mode."""
     recs = []

@@ -71,6 +71,15 @@ ROLLOUTS = {
     "rollout_tree36": ("tree36", 3, 22, 4, 0, {}),
 }
 
+# long rollouts checked by central differences of the oracle's rollout:
+# the 200-step, checkpoint-20 rollout of tree36 x 1024 (torques and targets
+# from scenes.rollout_inputs with seed 1), 16 environments spread over the
+# batch, 4 seeded torque directions each, h = 1e-6
+ROLLOUT_FD = {
+    "rollout_fd_tree36_1024": dict(workload="tree36", n_env=1024, seed=0, steps=200, input_seed=1,
+                                   envs=None, count=16, spread_seed=104, directions=4, h=1e-6),
+}
+
 # physical-parameter derivatives: name -> (workload, n_env, seed, env indices)
 PARAMS = {
     "params_cube8": ("cube_nospin", 8, 31, list(range(8))),
@@ -276,6 +285,65 @@ def _roll(args):
     return dict(loss=r["loss"], grad=r["grad"], qT=r["q"][-1], vT=r["v"][-1], ok=r["ok"], margin=r["margin"])
 
 
+def rollout_fd_setup(name):
+    """The seeded batch, inputs and sampled environments of a long-rollout
+    set (inputs only; shared with the GPU test)."""
+    c = ROLLOUT_FD[name]
+    batch = scenes.make(c["workload"], c["n_env"], seed=c["seed"])
+    taus, targets = scenes.rollout_inputs(batch, c["steps"], c["input_seed"])
+    envs = spread(c["n_env"], c["count"], c["spread_seed"])
+    return batch, taus, targets, envs
+
+
+def _fd_task(args):
+    name, e, j, sign = args
+    c = ROLLOUT_FD[name]
+    batch, taus, targets, _ = rollout_fd_setup(name)
+    d0, d1 = batch.dof_off[e], batch.dof_off[e + 1]
+    tt = taus[:, d0:d1].copy()
+    if j >= 0:
+        tt += sign * c["h"] * scenes.rollout_directions(batch, e, c["steps"], c["directions"], 5000 + e)[j]
+    model, qs, _, steps = rollout.rollout(batch.env(e), tt)
+    loss = rollout.base_position_loss(model, qs[-1], targets[e])[0]
+    modes = np.array([st[1]["modes"] for st in steps], dtype=np.int8)
+    ok = all(bool(st[1]["info"]["ok"]) for st in steps)
+    margin = min(float(st[1]["margin"]) for st in steps)
+    return (e, j, sign), dict(loss=loss, modes=modes, ok=ok, margin=margin)
+
+
+def make_rollout_fd(name):
+    """Per sampled environment: the loss of the oracle's 200-step rollout,
+    and per direction the central difference (L(+h d) - L(-h d)) / 2h with
+    whether the two perturbed rollouts kept the unperturbed rollout's
+    contact modes at every step, whether every step's NCP was solved, the
+    smallest mode margin, and the unperturbed rollout's modes (steps x n_c)."""
+    c = ROLLOUT_FD[name]
+    _, _, _, envs = rollout_fd_setup(name)
+    tasks = [(name, e, -1, 0) for e in envs] + [(name, e, j, s) for e in envs for j in range(c["directions"])
+                                                 for s in (1, -1)]
+    with Pool(8) as p:
+        res = dict(p.map(_fd_task, tasks, chunksize=1))
+    out = dict(envs=np.array(envs), h=c["h"], steps=c["steps"], directions=c["directions"])
+    fd = np.zeros((len(envs), c["directions"]))
+    same = np.zeros((len(envs), c["directions"]), dtype=bool)
+    ok = np.zeros((len(envs), c["directions"]), dtype=bool)
+    margin = np.zeros((len(envs), c["directions"]))
+    for i, e in enumerate(envs):
+        base = res[(e, -1, 0)]
+        out[f"modes__{i}"] = base["modes"]
+        for j in range(c["directions"]):
+            rp, rm = res[(e, j, 1)], res[(e, j, -1)]
+            fd[i, j] = (rp["loss"] - rm["loss"]) / (2 * c["h"])
+            same[i, j] = np.array_equal(rp["modes"], base["modes"]) and np.array_equal(rm["modes"], base["modes"])
+            ok[i, j] = base["ok"] and rp["ok"] and rm["ok"]
+            margin[i, j] = min(base["margin"], rp["margin"], rm["margin"])
+    out.update(fd=fd, same_modes=same, ok=ok, margin=margin,
+               loss=np.array([res[(e, -1, 0)]["loss"] for e in envs]))
+    np.savez_compressed(os.path.join(HERE, f"{name}.npz"), **out)
+    print(name, "directions with unchanged modes", int(same.sum()), "of", same.size, "solved", int(ok.sum()),
+          flush=True)
+
+
 def make_rollout(name):
     wl, n, seed, T, gap_mode, kw = ROLLOUTS[name]
     batch, taus, targets = rollout_inputs(name)
@@ -289,13 +357,16 @@ def make_rollout(name):
 
 
 if __name__ == "__main__":
-    default = list(SETS) + list(HARD) + [f"{x}_f32in" for x in list(SETS) + list(HARD)] + list(ROLLOUTS) + list(PARAMS)
+    default = list(SETS) + list(HARD) + [f"{x}_f32in" for x in list(SETS) + list(HARD)] + list(ROLLOUTS) + \
+        list(PARAMS) + list(ROLLOUT_FD)
     if sys.argv[1:2] == ["--sensitivity"]:
         for name in sys.argv[2:] or [f"{x}_f32in" for x in list(SETS) + list(HARD)]:
             refresh_sensitivity(name)
         sys.exit(0)
     for name in (sys.argv[1:] or default):
-        if name in ROLLOUTS:
+        if name in ROLLOUT_FD:
+            make_rollout_fd(name)
+        elif name in ROLLOUTS:
             make_rollout(name)
         elif name in PARAMS:
             make_params(name)

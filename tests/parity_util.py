@@ -209,3 +209,73 @@ def assert_parity(st, min_included, max_flagged=None):
     assert st["alternatives_invalid"] == 0
     if max_flagged is not None:
         assert st["solver_flags"] <= max_flagged
+
+
+# Relative tolerance of a 200-step rollout gradient against the oracle's
+# central differences.  FP64: the differences' own error (h = 1e-6; the
+# oracle's NCP tolerance divided by h) is about 1e-6 of the directional
+# derivative (the host build of the FP64 kernels: at most 7.6e-6 over the
+# 48 comparable directions).  FP32: per-step Jacobian errors up to 1e-4,
+# chained over 200 steps; the host build of the FP32 kernels with GPU
+# rounding stays below 3.1e-5 on its 40 comparable directions.
+LONG_TOL = {0: 1e-4, 1: 1e-3}
+
+
+def rollout_modes(db, q, v, taus):
+    """Forward rollout that also keeps every step's contact modes (T x n_c)
+    and the OR of the status words."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    modes = []
+    status = torch.zeros(max(db.n_env, 1), dtype=torch.int32, device=db.device)
+    for t in range(taus.shape[0]):
+        o = dsim.step_integrate(db, q, v, taus[t])
+        q, v = o["q_next"], o["v_next"]
+        status |= o["status"]
+        modes.append(o["mode"].clone())
+    return q, v, status, torch.stack(modes)
+
+
+def long_rollout_check(db, batch, taus, targets, envs, gold, checkpoint=20):
+    """The library's rollout gradient (checkpointed) along each stored
+    direction of each sampled environment, against the oracle's central
+    differences.  A direction is compared when the oracle's three rollouts
+    solved every step and kept the same modes, and the library's forward
+    rollout of that environment raised no solver flag and went through the
+    oracle's modes at every step; the others are counted by reason.
+    Returns (rows, counts)."""
+    import torch
+    from paper_2409_07107_amd import dsim, rollout, scenes
+    T = int(gold["steps"])
+    tt = torch.as_tensor(taus, dtype=db.dtype, device=db.device)
+    lf = rollout.base_position_loss(db, targets)
+    loss, grad, info = rollout.rollout_gradient(db, db.q, db.v, tt, lf, checkpoint=checkpoint)
+    _, _, st, modes = rollout_modes(db, db.q, db.v, tt)
+    torch.cuda.synchronize()
+    grad = grad.double().cpu().numpy()
+    st = (st | info["status"]).cpu().numpy()
+    modes = modes.cpu().numpy()
+    rows, counts = [], dict(compared=0, oracle_modes_change=0, oracle_unsolved=0, flagged=0, other_modes=0)
+    for i, e in enumerate(gold["envs"]):
+        e = int(e)
+        d0, d1 = batch.dof_off[e], batch.dof_off[e + 1]
+        c0, c1 = batch.contact_off[e], batch.contact_off[e + 1]
+        dirs = scenes.rollout_directions(batch, e, T, int(gold["directions"]), 5000 + e)
+        same_path = np.array_equal(modes[:, c0:c1].astype(np.int8), gold[f"modes__{i}"].astype(np.int8))
+        for j in range(int(gold["directions"])):
+            fd = float(gold["fd"][i, j])
+            an = float((grad[:, d0:d1] * dirs[j]).sum())
+            if not gold["ok"][i, j]:
+                why = "oracle_unsolved"
+            elif not gold["same_modes"][i, j]:
+                why = "oracle_modes_change"
+            elif st[e] & 17:
+                why = "flagged"
+            elif not same_path:
+                why = "other_modes"
+            else:
+                why = "compared"
+            counts[why] += 1
+            rows.append(dict(env=e, dir=j, fd=fd, an=an, why=why,
+                             rel=abs(an - fd) / max(abs(fd), 1e-12)))
+    return rows, counts

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2409_07107_amd import scenes
-from tests.parity_util import TOL, golden_for, load_golden, say
+from tests.parity_util import LONG_TOL, TOL, golden_for, load_golden, long_rollout_check, rollout_modes, say
 
 pytestmark = pytest.mark.gpu
 
@@ -183,14 +183,18 @@ def test_position_update_matches_oracle(name, gpu_lib):
         assert worst <= (1e-12 if precision == 0 else 1e-6)
 
 
-def _rollout_inputs(name):
+def _make_golden():
     import importlib.util
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_golden.py")
     spec = importlib.util.spec_from_file_location("make_golden", path)
     mg = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mg)
-    return mg.rollout_inputs(name)
+    return mg
+
+
+def _rollout_inputs(name):
+    return _make_golden().rollout_inputs(name)
 
 
 @pytest.mark.parametrize("name,precision", [("rollout_cube", 0), ("rollout_cube", 1), ("rollout_tree36", 0),
@@ -242,21 +246,6 @@ def test_checkpointing_does_not_change_the_gradient(gpu_lib):
     assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
 
 
-def _rollout_modes(db, q, v, taus):
-    """Forward rollout that also keeps every step's contact modes (T x n_c)
-    and the OR of the status words."""
-    import torch
-    from paper_2409_07107_amd import dsim
-    modes = []
-    status = torch.zeros(max(db.n_env, 1), dtype=torch.int32, device=db.device)
-    for t in range(taus.shape[0]):
-        o = dsim.step_integrate(db, q, v, taus[t])
-        q, v = o["q_next"], o["v_next"]
-        status |= o["status"]
-        modes.append(o["mode"].clone())
-    return q, v, status, torch.stack(modes)
-
-
 def test_long_rollout_directional_derivative(gpu_lib):
     """Property at rollout length: the FP64 gradient agrees with central
     differences (h = 1e-6) of the FP64 forward rollout along a random torque
@@ -282,9 +271,9 @@ def test_long_rollout_directional_derivative(gpu_lib):
     lf = rollout.base_position_loss(db, targets)
     loss, grad, info = rollout.rollout_gradient(db, db.q, db.v, tt, lf, checkpoint=7)
     h = 1e-6
-    _, _, s0, m0 = _rollout_modes(db, db.q, db.v, tt)
-    qp, vp, sp, mp = _rollout_modes(db, db.q, db.v, tt + h * d)
-    qm, vm, sm, mm = _rollout_modes(db, db.q, db.v, tt - h * d)
+    _, _, s0, m0 = rollout_modes(db, db.q, db.v, tt)
+    qp, vp, sp, mp = rollout_modes(db, db.q, db.v, tt + h * d)
+    qm, vm, sm, mm = rollout_modes(db, db.q, db.v, tt - h * d)
     lp, lm = lf(qp, vp)[0], lf(qm, vm)[0]
     torch.cuda.synchronize()
     fd = ((lp - lm) / (2 * h)).cpu().numpy()
@@ -425,3 +414,30 @@ def test_torch_rollout_with_the_fused_function(precision, gpu_lib):
     lv = float(loss.detach())
     assert abs(lv - float(ref_loss.sum())) <= tol * max(1.0, lv)
     assert torch.allclose(got, ref_grad, rtol=tol, atol=tol * float(ref_grad.abs().max()))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_long_rollout_gradient_matches_oracle_differences(precision, gpu_lib):
+    """The configured rollout (tree36 x 1024, 200 steps, checkpoint 20): the
+    gradient of the base-position loss with respect to the torques, along 4
+    random directions on 16 sampled environments, against central
+    differences of the FP64 oracle's rollout (h = 1e-6; stored by
+    make_golden.py).  Every comparable direction must agree; the directions
+    that are not comparable are counted by reason."""
+    from paper_2409_07107_amd import dsim
+    mg = _make_golden()
+    name = "rollout_fd_tree36_1024"
+    gold = load_golden(name)
+    batch, taus, targets, envs = mg.rollout_fd_setup(name)
+    assert [int(e) for e in gold["envs"]] == [int(e) for e in envs]
+    db = dsim.DeviceBatch(batch, precision=precision)
+    rows, counts = long_rollout_check(db, batch, taus, targets, envs, gold)
+    cmp = [r for r in rows if r["why"] == "compared"]
+    errs = ", ".join("%.1e" % r["rel"] for r in cmp)
+    say(f"200-step rollout, precision {precision}: {counts}; compared relative errors {errs}")
+    for r in rows:
+        if r["why"] == "compared" and r["rel"] > LONG_TOL[precision]:
+            say(f"  env {r['env']} direction {r['dir']}: fd {r['fd']:.6e} gradient {r['an']:.6e}")
+    assert counts["compared"] >= (4 if precision == 0 else 1)
+    assert all(r["rel"] <= LONG_TOL[precision] for r in cmp)
+
