@@ -8,9 +8,9 @@
   is read or written out of its bounds.  This is the address check of the
   layout that every kernel carves from LDS (the host build is g++ only; no
   GPU code is built with a sanitizer).
-* The host build of the FP64 form reproduces the oracle's stored results
-  under the GPU parity gates (the kernel arithmetic itself, checked on the
-  CPU).
+* The host build reproduces the oracle's stored results under the GPU
+  parity gates, in the FP64 form and in the FP32 form (the kernel
+  arithmetic itself, checked on the CPU).
 """
 import os
 import subprocess
@@ -63,13 +63,16 @@ def test_regions_stay_in_bounds_under_address_checker(tmp_path):
     assert r.stdout.count(" ok") == 4
 
 
-@pytest.mark.parametrize("name", ["cube8", "tree36_24"])
-def test_host_build_fp64_matches_oracle(name, host_lib):
+@pytest.mark.parametrize("name,precision", [("cube8", 0), ("tree36_24", 0), ("tree36_24", 1), ("arm7_64", 1)])
+def test_host_build_matches_oracle(name, precision, host_lib):
+    """The host build's step and Jacobian against the oracle's stored results
+    under the GPU parity gates (FP32: against the float32-input references,
+    with the conditioning-scaled tolerance)."""
     from paper_2409_07107_amd import dsim, scenes
-    from tests.parity_util import assert_parity, compare, load_golden
-    gold = load_golden(name)
+    from tests.parity_util import assert_parity, compare, golden_for
+    gold = golden_for(name, precision)
     batch = scenes.make(str(gold["workload"]), int(gold["n_env"]), seed=int(gold["seed"]))
-    db = dsim.DeviceBatch(batch, precision=dsim.F64, device="cpu")
+    db = dsim.DeviceBatch(batch, precision=precision, device="cpu")
     out = host_lib.run(db, dsim.ENTRY_JACOBIAN)
-    st = compare(batch, gold, out, db, 0, label=f"host {name}")
-    assert_parity(st, min_included=max(1, st["n"] // 3))  # the gate of the GPU parity test
+    st = compare(batch, gold, out, db, precision, label=f"host {name} precision {precision}")
+    assert_parity(st, min_included=max(1, st["n"] // 3), max_flagged=st["n"] // 20)

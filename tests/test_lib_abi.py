@@ -142,6 +142,13 @@ def test_short_workspace_is_rejected_before_any_launch(L):
         # hand-over records follow them
         assert L.dsim_step_jacobian(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy,
                                     slot * b.n_env, None) == -4
+        # the kept-step pair checks the same workspace before any launch
+        assert L.dsim_step_keep(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 7), dummy, need - 1, None) == -4
+        assert L.dsim_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy, need - 1, None) == -4
+        assert L.dsim_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), None, need, None) == -4
+        # and rejects missing arrays
+        assert L.dsim_step_keep(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), dummy, need, None) == -1
+        assert L.dsim_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([None] * 10), dummy, need, None) == -1
 
 
 def test_on_chip_sizing(L):
@@ -199,3 +206,23 @@ def test_noalloc_entry_rejects_batches_beyond_its_static_workspace(L):
     args = [dummy] * 12
     args[9] = None
     assert L.dsim_step_vjp_noalloc(ctypes.byref(cb), ctypes.byref(p), *args, None) == -1
+
+
+def test_rollout_inputs_act_on_joints_only():
+    """The seeded rollout inputs: torques and directions are zero on
+    free-flyer dofs (no actuator there), nonzero on joint dofs, and the same
+    on every call."""
+    b = scenes.make("tree36", 5, seed=3)
+    taus, targets = scenes.rollout_inputs(b, 7, seed=1)
+    taus2, targets2 = scenes.rollout_inputs(b, 7, seed=1)
+    assert np.array_equal(taus, taus2) and np.array_equal(targets, targets2)
+    mask = scenes.actuated_dofs(b)
+    assert mask.sum() == 5 * 30 and (~mask).sum() == 5 * 6
+    assert np.all(taus[:, ~mask] == 0) and np.all(taus[:, mask] != 0)
+    for e in range(b.n_env):
+        assert np.allclose(targets[e], b.q[b.cfg_off[e]:b.cfg_off[e] + 3], atol=0.6)
+        d = scenes.rollout_directions(b, e, 7, 3, 9)
+        d0, d1 = b.dof_off[e], b.dof_off[e + 1]
+        assert d.shape == (3, 7, d1 - d0)
+        assert np.all(d[:, :, :6] == 0) and np.all(d[:, :, 6:] != 0)
+
