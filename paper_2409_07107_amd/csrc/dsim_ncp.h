@@ -538,6 +538,34 @@ DSIM_HD inline void lu_solve(const double* A, int m, int rank, const int* rperm,
     for (int i = 0; i < m; ++i) x[cperm[i]] = y[i];
 }
 
+// lu_solve on wavefront 0: lane r keeps y_r in a register; the forward and
+// back substitutions go column by column, broadcasting each finished y_i
+// with a cross-lane shuffle (m <= 63).  The host build runs lu_solve.
+DSIM_HD inline void wave_lu_solve(const Team& T, const double* A, int m, int rank, const int* rperm,
+                                  const int* cperm, const double* b, double* y, double* x) {
+#ifdef DSIM_HOST_BUILD
+    lu_solve(A, m, rank, rperm, cperm, b, y, x);
+#else
+    (void)y;
+    const int r = T.lane;
+    double yr = r < m ? b[rperm[r]] : 0.0;
+    for (int i = 0; i < rank; ++i) {
+        const double yi = __shfl(yr, i, 64);
+        if (r > i && r < rank) yr -= A[r * m + i] * yi;
+    }
+    if (r >= rank) yr = 0.0;
+    for (int i = rank - 1; i >= 0; --i) {
+        const double yi = __shfl(yr, i, 64) / A[i * m + i];
+        if (r == i)
+            yr = yi;
+        else if (r < i)
+            yr -= A[r * m + i] * yi;
+    }
+    if (r < m) x[cperm[r]] = yr;
+    T.wave_sync();
+#endif
+}
+
 // Newton system of the mode equations (Section III.B) in the impulses of the
 // active contacts (3 unknowns each, sticking contacts first): sticking
 // sigma_c = 0; sliding Lam_T + mu Lam_N u = 0 (u = sigma_T/|sigma_T|) and
@@ -748,7 +776,7 @@ DSIM_INLINE DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
         if (since >= P.newton_iters) break;
         ++since;
         factor_A(T, E, P.rank_tol);
-        if (T.tid == 0) lu_solve(E.A, m, E.hdr[4], E.rperm, E.cperm, E.rhs, E.ytmp, E.X);
+        if (T.wave == 0) wave_lu_solve(T, E.A, m, E.hdr[4], E.rperm, E.cperm, E.rhs, E.ytmp, E.X);
         T.sync();
         for (int i = T.tid; i < m; i += T.nt) E.Ld[3 * E.vctc[i] + E.vcmp[i]] += E.X[i];
         T.sync();
@@ -764,7 +792,7 @@ DSIM_INLINE DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
         for (int r = T.tid; r < k; r += T.nt) E.Ld1[r] = E.Ld[r];
         T.sync();
         factor_A(T, E, P.rank_tol);
-        if (T.tid == 0) lu_solve(E.A, m, E.hdr[4], E.rperm, E.cperm, E.rhs, E.ytmp, E.X);
+        if (T.wave == 0) wave_lu_solve(T, E.A, m, E.hdr[4], E.rperm, E.cperm, E.rhs, E.ytmp, E.X);
         T.sync();
         for (int i = T.tid; i < m; i += T.nt) E.Ld[3 * E.vctc[i] + E.vcmp[i]] += E.X[i];
         T.sync();
