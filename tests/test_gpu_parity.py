@@ -123,3 +123,35 @@ def test_empty_batch_and_no_contacts(gpu_lib):
         tol = TOL[prec]["jac"]
         assert np.linalg.norm(J - dref["jac"]) <= tol * np.linalg.norm(dref["jac"])
         assert int(out["status"][1]) == 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solver_work_counters(precision, gpu_lib):
+    """The work each environment's solve reports in the workspace
+    (DSIM_WS_WORK) is consistent with its outputs: first-pass sweeps within
+    the configured rounds x sweeps, and at least one for an environment with
+    contacts; fallback work exactly for the environments the first pass left
+    unsolved (its marker), whose final status is then either solved or
+    flagged; and a flagged environment always went through the fallback."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    batch = scenes.make("tree36", 2048, seed=0)
+    db = dsim.DeviceBatch(batch, precision=precision)
+    p = db.params()
+    out = dsim.step_jacobian(db, p=p)
+    torch.cuda.synchronize()
+    w = dsim.solver_work(db, p)
+    ws, _ = db.workspace(p, dsim.ENTRY_JACOBIAN)
+    marker = ws[:batch.n_env * dsim.WS_ENV_DOUBLES * 8].view(torch.float64).reshape(batch.n_env, -1)[
+        :, dsim.WS_WORK + 4].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    nc = np.diff(batch.contact_off)
+    assert np.all(w["sweeps"] <= p.ncp_rounds * p.ncp_sweeps)
+    assert np.all(w["sweeps"][nc > 0] >= 1)
+    fb = marker != 0
+    assert np.array_equal(fb, w["lm_iterations"] > 0)
+    assert np.all(w["lm_solves"][~fb] == 0) and np.all(w["admm_iterations"][~fb] == 0)
+    assert np.all(fb[(st & 17) != 0])
+    say(f"precision {precision}: sweeps mean {w['sweeps'].mean():.1f} max {w['sweeps'].max()}; fallback "
+        f"{int(fb.sum())} of {batch.n_env}, still flagged {int(((st & 17) != 0).sum())}; Levenberg-Marquardt "
+        f"{int(w['lm_iterations'].sum())} iterations, ADMM {int(w['admm_iterations'].sum())} iterations")
