@@ -304,6 +304,8 @@ def run(args):
         "accuracy": {"fp32": r32["accuracy"], "fp64": r64["accuracy"]},
         "cpu_baseline": cpu,
         "status_flagged": {"fp32": flagged32, "fp64": flagged64},
+        "mode_mix": {name: float(np.mean(r32["modes"][:int(batch.contact_off[-1])] == code))
+                     for name, code in (("break", 0), ("stick", 1), ("slide", 2))},
     }
     print(json.dumps(line), flush=True)
 
