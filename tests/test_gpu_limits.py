@@ -37,8 +37,8 @@ def _box21(v):
 def _check(batch, db, out, r, precision, label, jac=None):
     """Every output of environment 0 against the oracle's forward result `r`
     (and, when given, its Jacobian `jac`): v+ and J^T Lam always (both
-unique for every NCP solution), the
-    impulses against every NCP condition for the oracle's (G, g, mu), and the
+    unique for every NCP solution), the impulses against every NCP condition
+    for the oracle's (G, g, mu), and the
     Jacobian where the modes agree at a margin above the floor, with the
     near-switch tolerance below `margin` (at a margin below the floor the
     one-sided derivatives differ and the Jacobian is reported only).  A solver
