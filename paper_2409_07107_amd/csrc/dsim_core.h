@@ -62,6 +62,30 @@ struct Team {
 #endif
 };
 
+// Wavefront 0 of a team working alone: the same code as for a whole team,
+// with the wavefront's barrier in place of the team's.  Chains of small
+// dependent steps (the refinement's Newton iterations and factorisations)
+// run on it, so that each step costs a wavefront barrier instead of a
+// workgroup barrier; the other wavefronts wait at the next team barrier.
+struct WaveTeam : Team {
+#ifdef DSIM_HOST_BUILD
+    void sync() const {}
+#else
+    __device__ void sync() const { wave_sync(); }
+#endif
+};
+
+// The wavefront-0 view of team T (called by the threads of wavefront 0).
+DSIM_HD inline WaveTeam wave_team(const Team& T) {
+    WaveTeam W;
+    W.tid = T.lane;
+    W.nt = T.nt < T.wsize ? T.nt : T.wsize;
+    W.lane = T.lane;
+    W.wave = 0;
+    W.wsize = T.wsize;
+    return W;
+}
+
 // Slots of the team reductions: three per wavefront of the largest team
 // (512 threads, 8 wavefronts; team_max2 stores a pair per wavefront and the
 // natural map's sum one more); the host build (a debugging build whose team
@@ -78,7 +102,8 @@ constexpr int kRedSlots = 3 * 8;
 // comparison picks.  Threads without a candidate pass (-1, INT_MAX).  Every
 // thread gets the result.  The slots are reused: a caller separates two
 // calls by at least one team barrier after the first call returns.
-DSIM_HD inline void team_argmax(const Team& T, double* redv, int* redi, double& v, int& i) {
+template <class TT>
+DSIM_HD inline void team_argmax(const TT& T, double* redv, int* redi, double& v, int& i) {
 #ifdef DSIM_HOST_BUILD
     redv[T.tid] = v;
     redi[T.tid] = i;
@@ -117,7 +142,8 @@ DSIM_HD inline void team_argmax(const Team& T, double* redv, int* redi, double& 
 
 // Maxima of two values over the team (NaN never wins), returned to every
 // thread; the same slot reuse rule as team_argmax.
-DSIM_HD inline void team_max2(const Team& T, double* redv, double& a, double& b) {
+template <class TT>
+DSIM_HD inline void team_max2(const TT& T, double* redv, double& a, double& b) {
 #ifdef DSIM_HOST_BUILD
     redv[2 * T.tid] = a;
     redv[2 * T.tid + 1] = b;

@@ -289,8 +289,8 @@ DSIM_HD void update_sigma(const Team& T, Env<R>& E) {
 }
 
 // sigma = Gd Ld + gd in FP64.
-template <class R>
-DSIM_HD void fp64_sigma(const Team& T, Env<R>& E) {
+template <class R, class TT>
+DSIM_HD void fp64_sigma(const TT& T, Env<R>& E) {
     const int k = E.k;
     for (int r = T.tid; r < k; r += T.nt) {
         double s = E.gd[r];
@@ -412,8 +412,8 @@ DSIM_HD void build_A(const Team& T, Env<R>& E) {
 // variables to zero (basic solution).  Leaves L (unit, below the diagonal)
 // and U in A, the row and column permutations in rperm/cperm, the rank in
 // hdr[4].
-template <class R>
-DSIM_INLINE DSIM_HD void factor_A(const Team& T, Env<R>& E, double rank_tol) {
+template <class R, class TT>
+DSIM_INLINE DSIM_HD void factor_A(const TT& T, Env<R>& E, double rank_tol) {
     const int m = E.hdr[1];
     const int nst = 3 * E.hdr[2];
     double* A = E.A;
@@ -573,8 +573,8 @@ DSIM_HD inline void wave_lu_solve(const Team& T, const double* A, int m, int ran
 // contact and component; dsc[1] gets the scaled residual max |F_i| / scale
 // and dsc[3] its squared 2-norm (velocity rows scaled by the free-velocity
 // scale, impulse rows by the impulse scale).  Uses Ld and dsig.
-template <class R>
-DSIM_INLINE DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P) {
+template <class R, class TT>
+DSIM_INLINE DSIM_HD void newton_system(const TT& T, Env<R>& E, const Params& P) {
     const int k = E.k, nc = E.nc;
     // unknowns: every thread counts the active contacts (sticking first,
     // then sliding) and thread c fills the slots of contact c
@@ -694,9 +694,11 @@ DSIM_INLINE DSIM_HD void newton_system(const Team& T, Env<R>& E, const Params& P
 // increases the residual of the same mode set is halved once, then taken
 // (longer backtracking spent evaluations without helping: more environments
 // stalled than with the nearly plain Newton step).  Returns true on a
-// consistent solution.
-template <class R>
-DSIM_INLINE DSIM_HD bool polish(const Team& T, Env<R>& E, const Params& P) {
+// consistent solution (also left in hdr[6]).  Run by wavefront 0 alone
+// (T = wave_team of the environment's team): the iteration is a chain of
+// small dependent steps whose team barriers cost more than the arithmetic.
+template <class R, class TT>
+DSIM_INLINE DSIM_HD bool polish(const TT& T, Env<R>& E, const Params& P) {
     const int k = E.k, nc = E.nc;
     const int max_changes = 2 * nc + 2;
     int changes = 0, since = 0;
@@ -1242,7 +1244,9 @@ DSIM_HD bool fallback_solve(const Team& T, Env<R>& E, const Params& P) {
     const int k = E.k;
     for (int r = T.tid; r < k; r += T.nt) E.vdiag[r] = E.Ld[r];
     classify_modes(T, E, P);
-    bool ok = polish(T, E, P);
+    if (T.wave == 0) polish(wave_team(T), E, P);
+    T.sync();
+    bool ok = E.hdr[6] != 0;
     if (ok) {
         // the refinement solves the mode equations; its result is kept only
         // if it also meets the natural-map tolerance
@@ -1315,7 +1319,9 @@ DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P, const R* lam_s
             E.lmode0[c] = E.lmode[c];
         }
         T.sync();
-        ok = polish(T, E, P);
+        if (T.wave == 0) polish(wave_team(T), E, P);
+        T.sync();
+        ok = E.hdr[6] != 0;
         if (ok) {
             // the refinement solves the equations of its mode set; the
             // solution is taken when it also meets the natural-map
@@ -1338,7 +1344,8 @@ DSIM_HD void solve_ncp(const Team& T, Env<R>& E, const Params& P, const R* lam_s
         fp64_sigma(T, E);
         reduced_vars(T, E);
         build_A(T, E);
-        factor_A(T, E, P.rank_tol);
+        if (T.wave == 0) factor_A(wave_team(T), E, P.rank_tol);
+        T.sync();
     }
     if (T.tid == 0) {
         E.hdr[5] = (ok || k == 0) ? 0 : ST_POLISH;
