@@ -204,9 +204,11 @@ int32_t dsim_validate_params(const dsim_params* params);
  * environment's FP64 contact impulses and solver counts (DSIM_WS_ENV_DOUBLES doubles,
  * at the start of the workspace) and a record of the step's
  * quantities that the derivative reads (kinematics, inertias, M^-1, the
- * contact rows, the factorised reduced system, v+ and a+), sized by the
- * batch's max_* fields and the precision (about 36 KB for 31 bodies, 36 dofs
- * and 8 contacts in FP32).  The workspace is the caller's; it must not be
+ * contact rows, the factorised reduced system, v+ and a+) and of the contact
+ * system (G, g, v_f, a_f and the inverses of G's diagonal blocks) that the
+ * step's first pass hands from its assembly launch to its contact-solve
+ * launch, sized by the batch's max_* fields and the precision (about 42 KB
+ * for 31 bodies, 36 dofs and 8 contacts in FP32).  The workspace is the caller's; it must not be
  * shared by calls that may run concurrently. */
 size_t dsim_workspace_bytes(const dsim_batch* batch, const dsim_params* params, int32_t entry);
 
@@ -306,7 +308,7 @@ int32_t dsim_vjp_kept(const dsim_batch* batch, const dsim_params* params,
  * tight serving loops, harnesses that forbid hipMalloc).  Arguments, outputs
  * and results are those of dsim_step_vjp; the hand-over between its launches
  * lives in a static device array of dsim_noalloc_scratch_bytes() bytes
- * (64 MiB: about 1800 environments of 31 bodies, 36 dofs and 8 contacts in
+ * (64 MiB: about 1590 environments of 31 bodies, 36 dofs and 8 contacts in
  * FP32) that each GPU the library runs on holds until the process ends.  A
  * batch whose hand-over (dsim_workspace_bytes for DSIM_ENTRY_VJP) exceeds it
  * is rejected with DSIM_ERR_WORKSPACE before any device call; DSIM_ERR_DEVICE

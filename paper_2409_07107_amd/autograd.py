@@ -24,7 +24,7 @@ class DiffStep(torch.autograd.Function):
     Both outputs are differentiable; the impulse gradient uses the library's
     impulse derivative, one valid choice when contacts are redundant.  With
     keep, forward keeps the step's hand-over (`dsim_step_keep`, one
-    workspace per call, about 36 KB per 36-dof environment) and backward
+    workspace per call, about 41 KB per 36-dof environment) and backward
     runs only the reverse mode (`dsim_vjp_kept`); without, backward solves
     the step again (`dsim_step_vjp`) and forward stores only its inputs."""
 

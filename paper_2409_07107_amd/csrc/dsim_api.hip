@@ -100,9 +100,13 @@ size_t team_bytes(const dsim_batch* b, const dsim_params* p, int entry) {
 // a compute unit); the derivative launch of a large tree (one team per
 // compute unit, its LDS being the limit) is dense products that a larger team
 // spreads.  Measured on tree36 x 16384: FP32 19.5 ms with 128 threads,
-// 16.4 ms with 256, 14.9 ms with 512; FP64 17.7, 17.0 and 14.8 ms.
+// 16.4 ms with 256, 14.9 ms with 512; FP64 17.7, 17.0 and 14.8 ms.  The
+// NCP launch of a derivative entry (the contact solve alone, from the
+// record) uses one wavefront: its team-wide phases are short loops over the
+// contact rows.
 int team_threads(const dsim_params* p, const dsim_batch* b, int entry) {
     if (p->threads > 0) return p->threads;
+    if (entry == ENTRY_NCP) return 64;
     const bool big = b->max_dofs >= 24;
     return (entry_has_derivative(entry) && big) ? 512 : 128;
 }
@@ -319,6 +323,21 @@ SideStream* side_stream(hipStream_t caller) {
     return &ss;
 }
 
+// The first pass of a derivative entry's step: the ASM launch (the step up to
+// its contact system, written to each environment's record) and the NCP
+// launch (the contact solve and the rest of the step, from the record, in a
+// layout several times smaller: more teams share a compute unit during the
+// latency-bound iterations).  Same arithmetic as one step launch.
+template <class R>
+int first_pass(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+               void* v_next, void* lam, int8_t* mode, int32_t* status, double* ld, void* stream) {
+    int rc = launch_one<R, ENTRY_ASM>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                      nullptr, nullptr, nullptr, nullptr, ld, stream, 0);
+    if (rc) return rc;
+    return launch_one<R, ENTRY_NCP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                    nullptr, nullptr, nullptr, nullptr, ld, stream, 0);
+}
+
 // The step is two launches of the step kernel on the same stream: the first
 // pass of the solve over every environment, then its fallback pass, whose
 // workgroups exit at once for the environments the first pass solved (its
@@ -344,8 +363,7 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
     if (!ws || ws_bytes < handover_bytes(b, p)) return DSIM_ERR_WORKSPACE;
     if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
     double* ld = static_cast<double*>(ws);
-    int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
-                                       nullptr, nullptr, nullptr, nullptr, ld, stream, 0);
+    int rc = first_pass<R>(b, p, q, v, tau, v_next, lam, mode, status, ld, stream);
     if (rc) return rc;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     SideStream* side = fork ? side_stream(s) : nullptr;
@@ -388,12 +406,10 @@ int launch_half(int half, const dsim_batch* b, const dsim_params* p, const void*
     if (team_bytes(b, p, ENTRY) > kLdsLimit) return DSIM_ERR_SIZE;  // before any launch
     double* ld = static_cast<double*>(ws);
     if (half == 1) {
-        for (int pass = 0; pass < 2; ++pass) {
-            int rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status,
-                                               nullptr, nullptr, nullptr, nullptr, nullptr, ld, stream, pass);
-            if (rc) return rc;
-        }
-        return DSIM_SUCCESS;
+        int rc = first_pass<R>(b, p, q, v, tau, v_next, lam, mode, status, ld, stream);
+        if (rc) return rc;
+        return launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                         nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
     }
     return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, nullptr,
                                 nullptr, ld, stream);

@@ -184,6 +184,13 @@ enum { BRK = 0, STK = 1, SLD = 2 };
 // step, its VJP and the gradients in the body masses and friction
 // coefficients; the step, its Jacobian and the parameter columns
 enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP = 4, ENTRY_PVJP = 5, ENTRY_PJAC = 6 };
+// The first pass of a derivative entry's step as two launches (internal, not
+// entries of the C ABI): the tree recursions and the contact system (G, g,
+// the inverses of G's diagonal blocks, v_f, a_f) written to the hand-over
+// record (ASM), then the contact solve from that record in a much smaller
+// on-chip layout, so that more environment teams share a compute unit while
+// they iterate (NCP).
+enum { ENTRY_ASM = 7, ENTRY_NCP = 8 };
 // FP64 impulses handed from the step launch to the derivative launch: one
 // slot of 3 x (maximum contacts) per environment, followed by the work its
 // contact solve executed (read back for the flop count): Gauss-Seidel
@@ -365,10 +372,59 @@ DSIM_HD inline T* take(char*& p, size_t n, size_t& total) {
     return r;
 }
 
+// The layout of the NCP launch: the contact system, the solver's state and
+// the reduced system only (the tree quantities stay in the hand-over record).
+// Every other pointer is null.
+template <class R>
+DSIM_HD inline size_t carve_ncp(char* base, const Dims& d, Env<R>& E) {
+    size_t tot = 0;
+    char* p = base;
+    const int NV = d.NV, NC = d.NC, K = d.K, KK = K * K;
+    E = Env<R>{};
+    E.hdr = take<int>(p, 16, tot);
+    E.cmode = take<int>(p, NC, tot);
+    E.lmode = take<int>(p, NC, tot);
+    E.lmode0 = take<int>(p, NC, tot);
+    E.vctc = take<int>(p, K, tot);
+    E.vcmp = take<int>(p, K, tot);
+    E.rperm = take<int>(p, K, tot);
+    E.cperm = take<int>(p, K, tot);
+    E.vf = take<double>(p, NV, tot);
+    E.af = take<double>(p, NV, tot);
+    E.vn = take<double>(p, NV, tot);
+    E.ap = take<double>(p, NV, tot);
+    E.mu = take<R>(p, NC, tot);
+    E.Winv = take<R>(p, 9 * NC, tot);
+    E.g = take<R>(p, K, tot);
+    E.Lam = take<R>(p, K, tot);
+    E.sig = take<R>(p, K, tot);
+    E.Lam0 = take<R>(p, K, tot);
+    E.sig0 = take<R>(p, K, tot);
+    E.vrow = take<double>(p, 3 * K, tot);
+    E.vcol = take<double>(p, 3 * K, tot);
+    E.vdiag = take<double>(p, K, tot);
+    E.Gd = take<double>(p, KK, tot);
+    E.G = sizeof(R) == sizeof(double) ? reinterpret_cast<R*>(E.Gd) : take<R>(p, KK, tot);
+    E.gd = take<double>(p, K, tot);
+    E.Ld = take<double>(p, K, tot);
+    E.Ld1 = take<double>(p, K, tot);
+    E.dfr = take<double>(p, 4 * NC, tot);
+    E.A = take<double>(p, KK, tot);
+    E.rhs = take<double>(p, K, tot);
+    E.X = take<double>(p, K, tot);
+    E.ytmp = take<double>(p, K, tot);
+    E.dsig = take<double>(p, K, tot);
+    E.dsc = take<double>(p, 12, tot);
+    E.redv = take<double>(p, kRedSlots, tot);
+    E.redi = take<int>(p, kRedSlots, tot);
+    return tot;
+}
+
 // Carves the scratch of one environment team out of `base` (nullptr: only
 // sizes).  Returns the number of bytes.
 template <class R>
 DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
+    if (entry == ENTRY_NCP) return carve_ncp<R>(base, d, E);
     size_t tot = 0;
     char* p = base;
     const int NB = d.NB, NV = d.NV, NC = d.NC, K = d.K;
@@ -569,7 +625,9 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
 // record, sized by the launch's maxima.
 struct Handover {
     size_t Rw, pw, S, V, Iw, Ic, xw, Mi, dsig, vrow, vcol, vdiag, dfr, A, vn, ap, J, KT;
-    size_t rperm, cperm, vctc, vcmp, hdr, bytes;
+    size_t rperm, cperm, vctc, vcmp, hdr;
+    size_t Gd, gd, vf, af, Winv;  // the contact system, from the ASM launch to the NCP launch
+    size_t bytes;
 };
 
 template <class R>
@@ -606,6 +664,11 @@ DSIM_HD inline Handover handover_layout(const Dims& d) {
     h.vctc = at(K * sizeof(int));
     h.vcmp = at(K * sizeof(int));
     h.hdr = at(4 * sizeof(int));
+    h.Gd = at(K * K * D8);
+    h.gd = at(K * D8);
+    h.vf = at(NV * D8);
+    h.af = at(NV * D8);
+    h.Winv = at(9 * NC * sizeof(R));
     h.bytes = o;
     return h;
 }

@@ -9,13 +9,13 @@
 
 namespace dsim {
 
-// The step: kinematics, dynamics, factorisation, contacts, NCP, v+.  With a
-// hand-over record (`rec`, laid out by `H`), each quantity the derivative
-// phases read is also written there once it is final, before its storage
-// is reused.
+// The step: kinematics, dynamics, factorisation, contacts (step_assemble),
+// then NCP and v+ (step_finish).  With a hand-over record (`rec`, laid out by
+// `H`), each quantity the derivative phases read is also written there once
+// it is final, before its storage is reused.
 template <class R>
-DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
-                          const Handover* H, char* rec, const R* lam_start) {
+DSIM_HD void step_assemble(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
+                           const Handover* H, char* rec) {
     const int nb = E.nb, n = E.nv, k = E.k, nc = E.nc;
     kinematics(T, E, B, q);
     mass_matrix(T, E);
@@ -55,6 +55,59 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
         team_put(T, rec, H->J, E.J, k * n);
         T.sync();
     }
+}
+
+// The contact system of the step for the NCP launch: K^T, G (FP64), g
+// (FP64), the inverses of G's diagonal blocks, v_f and a_f.
+template <class R>
+DSIM_HD void put_contact_system(const Team& T, const Env<R>& E, const Handover& H, char* rec) {
+    const int n = E.nv, k = E.k;
+    team_put(T, rec, H.KT, E.KT, k * n);
+    team_put(T, rec, H.Gd, E.Gd, k * k);
+    team_put(T, rec, H.gd, E.gd, k);
+    team_put(T, rec, H.vf, E.vf, n);
+    team_put(T, rec, H.af, E.af, n);
+    team_put(T, rec, H.Winv, E.Winv, 9 * E.nc);
+}
+
+// The NCP launch's start: sizes and friction coefficients of environment e,
+// and the contact system from its record; G and g in working precision are
+// the roundings of their FP64 values, as the Delassus assembly forms them.
+// K^T stays in the record (E.KT points there).
+template <class R>
+DSIM_HD void load_contact_system(const Team& T, Env<R>& E, const BatchView<R>& B, int e, const Handover& H,
+                                 char* rec) {
+    E.e = e;
+    E.b0 = B.body_off[e];
+    E.d0 = B.dof_off[e];
+    E.q0 = B.cfg_off[e];
+    E.c0 = B.contact_off[e];
+    E.nb = B.body_off[e + 1] - E.b0;
+    E.nv = B.dof_off[e + 1] - E.d0;
+    E.nq = B.cfg_off[e + 1] - E.q0;
+    E.nc = B.contact_off[e + 1] - E.c0;
+    E.k = 3 * E.nc;
+    const int n = E.nv, k = E.k;
+    if (T.tid == 0)
+        for (int i = 0; i < 16; ++i) E.hdr[i] = 0;
+    for (int c = T.tid; c < E.nc; c += T.nt) E.mu[c] = B.mu[E.c0 + c];
+    team_get(T, rec, H.Gd, E.Gd, k * k);
+    team_get(T, rec, H.gd, E.gd, k);
+    team_get(T, rec, H.vf, E.vf, n);
+    team_get(T, rec, H.af, E.af, n);
+    team_get(T, rec, H.Winv, E.Winv, 9 * E.nc);
+    E.KT = reinterpret_cast<R*>(rec + H.KT);
+    T.sync();
+    if (static_cast<void*>(E.G) != static_cast<void*>(E.Gd))
+        for (int i = T.tid; i < k * k; i += T.nt) E.G[i] = R(E.Gd[i]);
+    for (int r = T.tid; r < k; r += T.nt) E.g[r] = R(E.gd[r]);
+    T.sync();
+}
+
+template <class R>
+DSIM_HD void step_finish(const Team& T, Env<R>& E, const Params& P, const Handover* H, char* rec,
+                         const R* lam_start) {
+    const int n = E.nv, k = E.k, nc = E.nc;
     solve_ncp(T, E, P, lam_start);
     // v+ = v_f + M^-1 J^T Lam and a+ = a_f + M^-1 J^T Lam / dt
     for (int i = T.tid; i < n; i += T.nt) {
@@ -65,7 +118,9 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
     }
     T.sync();
     if (rec) {
-        team_put(T, rec, H->KT, E.KT, k * n);
+        // (the NCP launch reads K^T in place)
+        if (static_cast<const void*>(E.KT) != static_cast<const void*>(rec + H->KT))
+            team_put(T, rec, H->KT, E.KT, k * n);
         team_put(T, rec, H->dsig, E.dsig, k);
         team_put(T, rec, H->vrow, E.vrow, 3 * k);
         team_put(T, rec, H->vcol, E.vcol, 3 * k);
@@ -86,6 +141,13 @@ DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const
         }
     }
     residual_and_flags(T, E, P);
+}
+
+template <class R>
+DSIM_HD void step_forward(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const R* q,
+                          const Handover* H, char* rec, const R* lam_start) {
+    step_assemble(T, E, B, P, q, H, rec);
+    step_finish(T, E, P, H, rec, lam_start);
 }
 
 // The step's quantities for the derivative, loaded from the record the step
@@ -902,39 +964,60 @@ DSIM_HD void param_columns(const Team& T, Env<R>& E, const BatchView<R>& B, cons
     T.sync();
 }
 
+// The step's FP64 impulses and the work its contact solve executed, into
+// the environment's slot of `ld`.
+template <class R>
+DSIM_HD void write_work(const Team& T, const Env<R>& E, const Params& P, double* ld) {
+    double* l = ld + size_t(E.e) * kLdStride;
+    for (int r = T.tid; r < E.k; r += T.nt) l[r] = E.Ld[r];
+    if (T.tid == 0) {
+        // executed solver work: the first pass writes its sweeps and
+        // clears the fallback's counts, the fallback pass (run only
+        // for the environments the first left unsolved) writes its own
+        if (P.pass == 0) {
+            l[kLdWork] = double(E.hdr[7]);
+            l[kLdFallback] = (E.hdr[5] & (ST_NCP | ST_POLISH)) ? 1.0 : 0.0;
+        }
+        l[kLdWork + 1] = double(E.hdr[8]);
+        l[kLdWork + 2] = double(E.hdr[3]);
+        l[kLdWork + 3] = double(E.hdr[15]);
+    }
+}
+
 // Full pipeline of one environment.
 //
 // The step entries (STEP, SINT) solve the step and write its outputs, and
 // the FP64 impulses to `ld` when given.  The derivative entries (JAC, VJP,
 // RVJP) run after a step launch over the same environments: they restore
-// the step from `ld` and the written modes, then differentiate it.
+// the step from `ld` and the written modes, then differentiate it.  The
+// first step pass of a derivative entry is the ASM launch (the step up to
+// its contact system, into the record) followed by the NCP launch (the rest
+// of the step from the record): the same arithmetic as one step launch.
 template <class R>
 DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const Dims& D, int entry,
                      int e, const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
                      int8_t* mode, int32_t* status, R* o1, R* o2, R* o3, R* o4, R* o5, double* ld) {
-    load_env(T, E, B, e, q, v, tau);
     // hand-over record of this environment (derivative entries only)
     const Handover H = handover_layout<R>(D);
     char* rec = ld ? handover_base(ld, B.n_env) + size_t(e) * H.bytes : nullptr;
-    if (!entry_has_derivative(entry)) {
+    if (entry == ENTRY_NCP) {
+        // no tree quantities in this launch's layout: sizes, friction
+        // coefficients and the contact system only
+        load_contact_system(T, E, B, e, H, rec);
+        step_finish(T, E, P, &H, rec, static_cast<const R*>(lam));
+        write_step(T, E, v_next, lam, mode, status);
+        write_work(T, E, P, ld);
+        T.sync();
+        return;
+    }
+    load_env(T, E, B, e, q, v, tau);
+    if (entry == ENTRY_ASM) {
+        step_assemble(T, E, B, P, q, &H, rec);
+        put_contact_system(T, E, H, rec);
+    } else if (!entry_has_derivative(entry)) {
         step_forward(T, E, B, P, q, rec ? &H : nullptr, rec, static_cast<const R*>(lam));
         write_step(T, E, v_next, lam, mode, status);
-        if (ld) {
-            double* l = ld + size_t(E.e) * kLdStride;
-            for (int r = T.tid; r < E.k; r += T.nt) l[r] = E.Ld[r];
-            if (T.tid == 0) {
-                // executed solver work: the first pass writes its sweeps and
-                // clears the fallback's counts, the fallback pass (run only
-                // for the environments the first left unsolved) writes its own
-                if (P.pass == 0) {
-                    l[kLdWork] = double(E.hdr[7]);
-                    l[kLdFallback] = (E.hdr[5] & (ST_NCP | ST_POLISH)) ? 1.0 : 0.0;
-                }
-                l[kLdWork + 1] = double(E.hdr[8]);
-                l[kLdWork + 2] = double(E.hdr[3]);
-                l[kLdWork + 3] = double(E.hdr[15]);
-            }
-        }
+        if (ld) write_work(T, E, P, ld);
         if (entry == ENTRY_SINT) integrate(T, E, P, q, o1);
     } else {
         load_step(T, E, H, rec, ld, mode);

@@ -167,14 +167,19 @@ def test_on_chip_sizing(L):
         # the derivative entries hand 63 FP64 impulses and the solver's
         # counts (DSIM_WS_ENV_DOUBLES doubles) per environment over from their
         # step launch, then one record of the step's quantities per
-        # environment; the step entries need no workspace
+        # environment (with the contact system that the first step pass
+        # hands from its assembly launch to its solve launch: G, g, v_f,
+        # a_f in FP64 and the inverses of G's diagonal blocks in working
+        # precision); the step entries need no workspace
         NB, NV, NQ, NC = b.max_sizes
         K = 3 * NC
         r = 4 if prec == dsim.F32 else 8
         pad = lambda nbytes: (nbytes + 15) // 16 * 16
         doubles = [9 * NB, 3 * NB, 6 * NV, 6 * NB, 10 * NB, 10 * NB, 3 * NC, NV * NV, K, 3 * K, 3 * K, K, 4 * NC,
                    K * K, NV, NV]
-        record = sum(pad(8 * x) for x in doubles) + 2 * pad(r * K * NV) + 4 * pad(4 * K) + pad(16)
+        system = [K * K, K, NV, NV]
+        record = sum(pad(8 * x) for x in doubles) + 2 * pad(r * K * NV) + 4 * pad(4 * K) + pad(16) + \
+            sum(pad(8 * x) for x in system) + pad(r * 9 * NC)
         expect = (b.n_env * dsim.WS_ENV_DOUBLES + 1) // 2 * 2 * 8 + b.n_env * record
         for entry in (dsim.ENTRY_JACOBIAN, dsim.ENTRY_VJP, dsim.ENTRY_STEP_INTEGRATE_VJP, dsim.ENTRY_VJP_PARAMS,
                       dsim.ENTRY_JACOBIAN_PARAMS):
