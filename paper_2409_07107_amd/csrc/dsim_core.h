@@ -337,7 +337,7 @@ struct Env {
     double* gint;  // adjoint of q carried through the position update
     double* scr;  // FP64 solve scratch, max(K, NV) x NV
     // working-precision quantities
-    R *mu, *Winv, *J, *KT, *G, *g, *Lam, *sig, *Lam0;
+    R *mu, *Winv, *J, *KT, *g, *Lam, *sig, *Lam0;
     R* sig0;      // step entries: sigma and modes at the end of the previous
     int* lmode0;  // sweep round (with Lam0, the impulses)
     R *dTq, *dTv, *E, *T, *P, *Q;
@@ -404,7 +404,6 @@ DSIM_HD inline size_t carve_ncp(char* base, const Dims& d, Env<R>& E) {
     E.vcol = take<double>(p, 3 * K, tot);
     E.vdiag = take<double>(p, K, tot);
     E.Gd = take<double>(p, KK, tot);
-    E.G = sizeof(R) == sizeof(double) ? reinterpret_cast<R*>(E.Gd) : take<R>(p, KK, tot);
     E.gd = take<double>(p, K, tot);
     E.Ld = take<double>(p, K, tot);
     E.Ld1 = take<double>(p, K, tot);
@@ -479,8 +478,8 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     //    then (once the Delassus operator is formed) the reduced-system
     //    matrix A; and one region for the body velocities, accelerations,
     //    forces and inertias of the dynamics (dead once RNEA and the mass
-    //    matrix are done), then M^-1 (dead once J M^-1 is formed), then Gd
-    //    and G.  Four teams of a 36-dof tree with 8 contacts then fit one
+    //    matrix are done), then M^-1 (dead once J M^-1 is formed), then Gd.
+    //    Four teams of a 36-dof tree with 8 contacts then fit one
     //    compute unit's LDS.
     const int NN = NV * NV, KK = K * K;
     double* un = nullptr;
@@ -500,12 +499,9 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.Mx = take<double>(p, mx, tot);
         E.scr = E.Mx;
         ax = E.Mx;
-        // Gd, then G in working precision (FP64 runs use Gd itself)
-        const size_t gpair =
-            size_t(KK) + (sizeof(R) == sizeof(double) ? 0 : (size_t(KK) * sizeof(R) + sizeof(double) - 1) / sizeof(double));
         size_t ur = size_t(38) * NB;
         if (ur < size_t(NN)) ur = size_t(NN);
-        if (ur < gpair) ur = gpair;
+        if (ur < size_t(KK)) ur = size_t(KK);
         if (in_j && ur < size_t(2) * KK) ur = size_t(2) * KK;
         double* u = take<double>(p, ur, tot);
         E.V = u;
@@ -540,12 +536,6 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
     } else {
         E.KT = take<R>(p, K * NV, tot);
     }
-    if (sizeof(R) == sizeof(double))
-        E.G = nullptr;  // set to Gd below
-    else if (deriv)
-        E.G = nullptr;  // the derivative launch forms no Delassus matrix
-    else
-        E.G = reinterpret_cast<R*>(gda + KK);
     E.g = take<R>(p, K, tot);
     E.Lam = take<R>(p, K, tot);
     E.sig = take<R>(p, K, tot);
@@ -567,7 +557,6 @@ DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
         E.vdiag = take<double>(p, K, tot);
     }
     E.Gd = gda ? gda : take<double>(p, KK, tot);
-    if (sizeof(R) == sizeof(double)) E.G = reinterpret_cast<R*>(E.Gd);
     E.gd = take<double>(p, K, tot);
     E.Ld = take<double>(p, K, tot);
     E.Ld1 = take<double>(p, K, tot);

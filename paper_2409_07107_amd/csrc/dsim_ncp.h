@@ -234,7 +234,9 @@ DSIM_HD inline int local_solve(const R* W, const R* Wi, const R* b, R mu, R* lam
 
 // At most `sweeps` block Gauss-Seidel sweeps, run by wavefront 0: sigma =
 // G Lam + g is kept up to date in LDS; each contact update is computed
-// redundantly by all lanes, then the lanes update sigma row-parallel.  A
+// redundantly by all lanes, then the lanes update sigma row-parallel.  G in
+// working precision is the rounding of the FP64 Delassus matrix, taken from
+// Gd as it is read (no second copy on chip).  A
 // sweep that changes no impulse and no mode has reached a fixed point in
 // working precision: every further sweep would repeat it exactly, so the
 // sweeps end there (the same result as running them all).
@@ -248,7 +250,7 @@ DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
                 const int o = 3 * c;
                 R W[9];
                 for (int i = 0; i < 3; ++i)
-                    for (int j = 0; j < 3; ++j) W[3 * i + j] = E.G[(o + i) * k + o + j];
+                    for (int j = 0; j < 3; ++j) W[3 * i + j] = R(E.Gd[(o + i) * k + o + j]);
                 const R L[3] = {E.Lam[o], E.Lam[o + 1], E.Lam[o + 2]};
                 R b[3];
                 for (int i = 0; i < 3; ++i)
@@ -261,7 +263,7 @@ DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
                 moved = moved || md != prev || !(d0 == R(0) && d1 == R(0) && d2 == R(0));
                 T.wave_sync();
                 for (int r = T.lane; r < k; r += T.wsize)
-                    E.sig[r] += E.G[r * k + o] * d0 + E.G[r * k + o + 1] * d1 + E.G[r * k + o + 2] * d2;
+                    E.sig[r] += R(E.Gd[r * k + o]) * d0 + R(E.Gd[r * k + o + 1]) * d1 + R(E.Gd[r * k + o + 2]) * d2;
                 if (T.lane == 0) {
                     E.Lam[o] = Ln[0];
                     E.Lam[o + 1] = Ln[1];
@@ -273,17 +275,6 @@ DSIM_HD void nsgs(const Team& T, Env<R>& E, int sweeps) {
             if (T.lane == 0) E.hdr[7] += 1;  // sweeps executed
             if (!moved) break;
         }
-    }
-    T.sync();
-}
-
-template <class R>
-DSIM_HD void update_sigma(const Team& T, Env<R>& E) {
-    const int k = E.k;
-    for (int r = T.tid; r < k; r += T.nt) {
-        R s = E.g[r];
-        for (int c = 0; c < k; ++c) s += E.G[r * k + c] * E.Lam[c];
-        E.sig[r] = s;
     }
     T.sync();
 }

@@ -71,8 +71,8 @@ DSIM_HD void put_contact_system(const Team& T, const Env<R>& E, const Handover& 
 }
 
 // The NCP launch's start: sizes and friction coefficients of environment e,
-// and the contact system from its record; G and g in working precision are
-// the roundings of their FP64 values, as the Delassus assembly forms them.
+// and the contact system from its record; g in working precision is the
+// rounding of its FP64 value, as the Delassus assembly forms it.
 // K^T stays in the record (E.KT points there).
 template <class R>
 DSIM_HD void load_contact_system(const Team& T, Env<R>& E, const BatchView<R>& B, int e, const Handover& H,
@@ -98,8 +98,6 @@ DSIM_HD void load_contact_system(const Team& T, Env<R>& E, const BatchView<R>& B
     team_get(T, rec, H.Winv, E.Winv, 9 * E.nc);
     E.KT = reinterpret_cast<R*>(rec + H.KT);
     T.sync();
-    if (static_cast<void*>(E.G) != static_cast<void*>(E.Gd))
-        for (int i = T.tid; i < k * k; i += T.nt) E.G[i] = R(E.Gd[i]);
     for (int r = T.tid; r < k; r += T.nt) E.g[r] = R(E.gd[r]);
     T.sync();
 }

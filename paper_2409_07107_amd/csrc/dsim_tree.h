@@ -399,8 +399,8 @@ DSIM_HD void contact_jacobian(const Team& T, Env<R>& E) {
 }
 
 // K^T = J M^-1 (k x n; FP64 solves, stored in working precision),
-// G = J M^-1 J^T accumulated in FP64 (kept as Gd, rounded to G for the
-// sweeps), g = J v_f (+ phi/dt on normal rows in gap mode 1), and the
+// G = J M^-1 J^T accumulated in FP64 (kept as Gd; the sweeps round it to
+// working precision as they read it), g = J v_f (+ phi/dt on normal rows in gap mode 1), and the
 // inverses of the 3x3 diagonal blocks of G for the local solves.
 template <class R>
 DSIM_HD void delassus(const Team& T, Env<R>& E, const Params& P) {
@@ -426,8 +426,6 @@ DSIM_HD void delassus(const Team& T, Env<R>& E, const Params& P) {
         for (int i = 0; i < n; ++i) s += x[i] * double(y[i]);
         E.Gd[a * k + c] = s;
         E.Gd[c * k + a] = s;
-        E.G[a * k + c] = R(s);
-        E.G[c * k + a] = R(s);
     }
     for (int r = T.tid; r < k; r += T.nt) {
         double s = 0;
