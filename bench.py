@@ -47,13 +47,14 @@ WORKLOADS = {
 }
 KERNEL = "env_kernel<float, jacobian>"
 STEP_KERNEL = "env_kernel<float, step>: assembly, contact-solve and fallback-pass launches"
-TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f"env_kernel_f32_step_{x}_pass_tree36_16384_traffic.json")
-                 for x in ("first", "fallback")]
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f"env_kernel_f32_step_{x}_tree36_16384_traffic.json")
+                 for x in ("assembly", "contact_solve", "fallback_pass")]
 
 
 def measured_traffic():
-    """HBM bytes of the step's two launches (first pass + fallback pass) of
-    a dsim_step_jacobian call, from the committed counter summaries
+    """HBM bytes of the step's three launches (the first pass's assembly and
+    contact-solve launches, the fallback pass) of a dsim_step_jacobian call,
+    from the committed counter summaries
     (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration),
     or None when absent or taken on other kernel sources."""
     from paper_2409_07107_amd.profiling import source_digest
