@@ -106,7 +106,7 @@ size_t team_bytes(const dsim_batch* b, const dsim_params* p, int entry) {
 // contact rows.
 int team_threads(const dsim_params* p, const dsim_batch* b, int entry) {
     if (p->threads > 0) return p->threads;
-    if (entry == ENTRY_NCP) return 64;
+    if (entry == ENTRY_NCP || entry == ENTRY_FBK) return 64;
     const bool big = b->max_dofs >= 24;
     return (entry_has_derivative(entry) && big) ? 512 : 128;
 }
@@ -344,10 +344,12 @@ int first_pass(const dsim_batch* b, const dsim_params* p, const void* q, const v
 // status output tells them) and recompute the others from the first pass's
 // impulses.  A hard environment's fallback then overlaps with the others'
 // instead of lengthening one team's chain of rounds.  A derivative entry
-// adds a third launch: the step launches have a small on-chip footprint
-// (several teams share a compute unit while they iterate on the contact
-// problem) and hand their FP64 impulses and other quantities over through
-// the workspace to the derivative launch, which loads them.
+// runs its first pass as two launches (first_pass) and its fallback pass
+// from the contact system in the record (FBK: no tree recursions again, the
+// small layout), then the derivative launch: the step launches have a small
+// on-chip footprint (several teams share a compute unit while they iterate
+// on the contact problem) and hand their FP64 impulses and other quantities
+// over through the workspace to the derivative launch, which loads them.
 template <class R, int ENTRY>
 int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
            const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
@@ -368,8 +370,8 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
     const hipStream_t s = static_cast<hipStream_t>(stream);
     SideStream* side = fork ? side_stream(s) : nullptr;
     if (!side) {
-        rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
-                                       nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
+        rc = launch_one<R, ENTRY_FBK>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                      nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
         if (rc) return rc;
         return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
                                     ld, stream);
@@ -380,8 +382,8 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
     std::lock_guard<std::mutex> lock(side->mutex);
     if (hipEventRecord(side->fork, s) != hipSuccess || hipStreamWaitEvent(side->stream, side->fork, 0) != hipSuccess)
         return DSIM_ERR_LAUNCH;
-    rc = launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr, nullptr,
-                                   nullptr, nullptr, nullptr, ld, side->stream, 1);
+    rc = launch_one<R, ENTRY_FBK>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr, nullptr,
+                                  nullptr, nullptr, nullptr, ld, side->stream, 1);
     const bool joined = hipEventRecord(side->join, side->stream) == hipSuccess;
     const int rc2 = launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
                                          ld, stream, 2);
@@ -408,8 +410,8 @@ int launch_half(int half, const dsim_batch* b, const dsim_params* p, const void*
     if (half == 1) {
         int rc = first_pass<R>(b, p, q, v, tau, v_next, lam, mode, status, ld, stream);
         if (rc) return rc;
-        return launch_one<R, ENTRY_STEP>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
-                                         nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
+        return launch_one<R, ENTRY_FBK>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
     }
     return launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, nullptr,
                                 nullptr, ld, stream);

@@ -189,8 +189,10 @@ enum { ENTRY_STEP = 0, ENTRY_JAC = 1, ENTRY_VJP = 2, ENTRY_SINT = 3, ENTRY_RVJP 
 // the inverses of G's diagonal blocks, v_f, a_f) written to the hand-over
 // record (ASM), then the contact solve from that record in a much smaller
 // on-chip layout, so that more environment teams share a compute unit while
-// they iterate (NCP).
-enum { ENTRY_ASM = 7, ENTRY_NCP = 8 };
+// they iterate (NCP).  The fallback pass of a derivative entry starts from
+// the same record (FBK: the NCP layout with the fallback solvers' second
+// k x k matrix).
+enum { ENTRY_ASM = 7, ENTRY_NCP = 8, ENTRY_FBK = 9 };
 // FP64 impulses handed from the step launch to the derivative launch: one
 // slot of 3 x (maximum contacts) per environment, followed by the work its
 // contact solve executed (read back for the flop count): Gauss-Seidel
@@ -372,11 +374,12 @@ DSIM_HD inline T* take(char*& p, size_t n, size_t& total) {
     return r;
 }
 
-// The layout of the NCP launch: the contact system, the solver's state and
-// the reduced system only (the tree quantities stay in the hand-over record).
-// Every other pointer is null.
+// The layout of the NCP and FBK launches: the contact system, the solver's
+// state and the reduced system only (the tree quantities stay in the
+// hand-over record), and for FBK the fallback's second k x k matrix.  Every
+// other pointer is null.
 template <class R>
-DSIM_HD inline size_t carve_ncp(char* base, const Dims& d, Env<R>& E) {
+DSIM_HD inline size_t carve_ncp(char* base, const Dims& d, Env<R>& E, bool fallback) {
     size_t tot = 0;
     char* p = base;
     const int NV = d.NV, NC = d.NC, K = d.K, KK = K * K;
@@ -409,6 +412,7 @@ DSIM_HD inline size_t carve_ncp(char* base, const Dims& d, Env<R>& E) {
     E.Ld1 = take<double>(p, K, tot);
     E.dfr = take<double>(p, 4 * NC, tot);
     E.A = take<double>(p, KK, tot);
+    E.A2 = fallback ? take<double>(p, KK, tot) : nullptr;
     E.rhs = take<double>(p, K, tot);
     E.X = take<double>(p, K, tot);
     E.ytmp = take<double>(p, K, tot);
@@ -423,7 +427,7 @@ DSIM_HD inline size_t carve_ncp(char* base, const Dims& d, Env<R>& E) {
 // sizes).  Returns the number of bytes.
 template <class R>
 DSIM_HD inline size_t carve(char* base, const Dims& d, int entry, Env<R>& E) {
-    if (entry == ENTRY_NCP) return carve_ncp<R>(base, d, E);
+    if (entry == ENTRY_NCP || entry == ENTRY_FBK) return carve_ncp<R>(base, d, E, entry == ENTRY_FBK);
     size_t tot = 0;
     char* p = base;
     const int NB = d.NB, NV = d.NV, NC = d.NC, K = d.K;

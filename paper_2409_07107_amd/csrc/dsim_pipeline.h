@@ -990,7 +990,8 @@ DSIM_HD void write_work(const Team& T, const Env<R>& E, const Params& P, double*
 // the step from `ld` and the written modes, then differentiate it.  The
 // first step pass of a derivative entry is the ASM launch (the step up to
 // its contact system, into the record) followed by the NCP launch (the rest
-// of the step from the record): the same arithmetic as one step launch.
+// of the step from the record), and its fallback pass the FBK launch (from
+// the same record): the same arithmetic as the step launches.
 template <class R>
 DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Params& P, const Dims& D, int entry,
                      int e, const R* q, const R* v, const R* tau, const R* gbar, const R* gbar2, R* v_next, R* lam,
@@ -998,7 +999,7 @@ DSIM_HD void run_env(const Team& T, Env<R>& E, const BatchView<R>& B, const Para
     // hand-over record of this environment (derivative entries only)
     const Handover H = handover_layout<R>(D);
     char* rec = ld ? handover_base(ld, B.n_env) + size_t(e) * H.bytes : nullptr;
-    if (entry == ENTRY_NCP) {
+    if (entry == ENTRY_NCP || entry == ENTRY_FBK) {
         // no tree quantities in this launch's layout: sizes, friction
         // coefficients and the contact system only
         load_contact_system(T, E, B, e, H, rec);

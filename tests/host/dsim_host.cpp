@@ -5,9 +5,9 @@
 // one thread.  This file instantiates that build: every environment of a
 // batch whose arrays are HOST memory is run through run_env exactly as one
 // workgroup of the GPU launch would run it, in the same launch order (the
-// two passes of the step launch over all environments -- the first as the
-// ASM and NCP launches in the derivative entries -- then the derivative
-// launch for the derivative entries).  It is a verification tool (address checking of each
+// two passes of the step launch over all environments -- in the derivative
+// entries the first as the ASM and NCP launches, the second as the FBK
+// launch -- then the derivative launch for the derivative entries).  It is a verification tool (address checking of each
 // scratch region, the solver's behaviour on chosen environments), never a
 // path of the library: the package has no CPU fallback.
 //
@@ -151,10 +151,11 @@ int run(const dsim_batch* b, const dsim_params* p, int entry, const void* q, con
         return 0;
     }
     // the first step pass as the ASM and NCP launches, then the fallback pass
+    // (FBK)
     for (int ent : {int(ENTRY_ASM), int(ENTRY_NCP)})
         pass<R>(b, p, ent, c(q), c(v), c(tau), nullptr, nullptr, w(v_next), w(lam), mode, status, nullptr, nullptr,
                 nullptr, nullptr, nullptr, ld, e0, e1, region, 0);
-    pass<R>(b, p, ENTRY_STEP, c(q), c(v), c(tau), nullptr, nullptr, w(v_next), w(lam), mode, status, nullptr,
+    pass<R>(b, p, ENTRY_FBK, c(q), c(v), c(tau), nullptr, nullptr, w(v_next), w(lam), mode, status, nullptr,
             nullptr, nullptr, nullptr, nullptr, ld, e0, e1, region, 1);
     return pass<R>(b, p, entry, c(q), c(v), c(tau), c(gbar), c(gbar2), w(v_next), w(lam), mode, status, w(o1), w(o2),
                    w(o3), w(o4), w(o5), ld, e0, e1, region);
