@@ -303,6 +303,23 @@ int32_t dsim_vjp_kept(const dsim_batch* batch, const dsim_params* params,
                       void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * ... or the full Jacobian of that step (eq. FD_grads with the reduced
+ * system of eq. 10 / Appendix B, assembled as in Appendix D) without solving
+ * it again: dvdq, dvdv, dvdtau laid out as in dsim_step_jacobian and equal
+ * to its outputs bit for bit, for the same batch, params, q, v and tau
+ * (ws_bytes at least dsim_workspace_bytes for DSIM_ENTRY_JACOBIAN, the same
+ * size as for DSIM_ENTRY_VJP; `mode` and `status` as in dsim_vjp_kept).
+ * One launch on `stream`, ordered after the dsim_step_keep call; it
+ * refuses, with DSIM_ERR_SIZE and before any launch, the trees whose
+ * derivative layout does not fit on chip, as dsim_step_jacobian does.
+ */
+int32_t dsim_jacobian_kept(const dsim_batch* batch, const dsim_params* params,
+                           const void* q, const void* v, const void* tau,
+                           const int8_t* mode, int32_t* status,
+                           void* dvdq, void* dvdv, void* dvdtau,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/*
  * dsim_step_vjp without a caller workspace and without any allocation, for
  * callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  Arguments, outputs

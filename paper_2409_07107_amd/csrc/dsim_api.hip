@@ -692,6 +692,21 @@ int32_t dsim_vjp_kept(const dsim_batch* b, const dsim_params* p, const void* q, 
                                           g_v, g_tau, ws, ws_bytes, stream);
 }
 
+int32_t dsim_jacobian_kept(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                           const void* tau, const int8_t* mode, int32_t* status, void* dvdq, void* dvdv,
+                           void* dvdtau, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !v || !tau || !status || !mode || !dvdq || !dvdv || !dvdtau || !b->jac_off) return DSIM_ERR_ARG;
+    int8_t* md = const_cast<int8_t*>(mode);  // read only by the derivative launch
+    if (p->precision == DSIM_F32)
+        return launch_half<float, ENTRY_JAC>(2, b, p, q, v, tau, nullptr, nullptr, nullptr, nullptr, md, status,
+                                             dvdq, dvdv, dvdtau, ws, ws_bytes, stream);
+    return launch_half<double, ENTRY_JAC>(2, b, p, q, v, tau, nullptr, nullptr, nullptr, nullptr, md, status, dvdq,
+                                          dvdv, dvdtau, ws, ws_bytes, stream);
+}
+
 int32_t dsim_step_vjp_params(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
                              const void* tau, const void* g_vnext, const void* g_lam, void* v_next, void* lam,
                              int8_t* mode, int32_t* status, void* g_q, void* g_v, void* g_tau, void* g_params,

@@ -29,7 +29,8 @@ SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
            "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params",
            "dsim_step_jacobian_params", "dsim_ambient_to_tangent", "dsim_status_string",
-           "dsim_step_keep", "dsim_vjp_kept", "dsim_step_vjp_noalloc", "dsim_noalloc_scratch_bytes")
+           "dsim_step_keep", "dsim_vjp_kept", "dsim_jacobian_kept", "dsim_step_vjp_noalloc",
+           "dsim_noalloc_scratch_bytes")
 
 _vp = ctypes.c_void_p
 
@@ -92,6 +93,9 @@ def lib():
         L.dsim_vjp_kept.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 10 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_vjp_kept.restype = ctypes.c_int32
+        L.dsim_jacobian_kept.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_jacobian_kept.restype = ctypes.c_int32
         L.dsim_step_vjp_noalloc.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13
         L.dsim_step_vjp_noalloc.restype = ctypes.c_int32
         L.dsim_noalloc_scratch_bytes.argtypes = []
@@ -346,6 +350,29 @@ def vjp_kept(db: DeviceBatch, kept, g_vnext, q=None, v=None, tau=None, p: CParam
                                _ptr(g_lam), _ptr(kept["mode"]), _ptr(out["status"]), _ptr(out["g_q"]),
                                _ptr(out["g_v"]), _ptr(out["g_tau"]), _ptr(ws), ctypes.c_size_t(ws.numel()),
                                ctypes.c_void_p(_stream())))
+    return out
+
+
+def jacobian_kept(db: DeviceBatch, kept, q=None, v=None, tau=None, p: CParams | None = None, out=None,
+                  cb=None):
+    """dsim_jacobian_kept: the full Jacobian of the step `kept` (step_keep's
+    output for the same q, v, tau and params) without solving it again:
+    dvdq, dvdv, dvdtau as step_jacobian returns them, and the step's status
+    with DSIM_ST_NONFINITE added for non-finite entries."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    c = db.c if cb is None else cb
+    if out is None:
+        out = {k: torch.empty(max(db.n_jac, 1), dtype=db.dtype, device=db.device) for k in ("dvdq", "dvdv", "dvdtau")}
+    out["status"] = kept["status"].clone()
+    ws = kept["kept"]
+    _check(lib().dsim_jacobian_kept(ctypes.byref(c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                                    _ptr(kept["mode"]), _ptr(out["status"]), _ptr(out["dvdq"]), _ptr(out["dvdv"]),
+                                    _ptr(out["dvdtau"]), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                    ctypes.c_void_p(_stream())))
     return out
 
 

@@ -122,18 +122,31 @@ def cmd_traffic(a):
     print(json.dumps(out, indent=1))
 
 
-def _label(name: str, alternate: list[str] | None, seen: dict) -> str:
+def _label(name: str, alternate, seen: dict) -> str:
+    """The label of this kernel's next dispatch: `alternate` is a list of
+    labels dealt in turn, or (labels, n, rest): the first n dispatches dealt
+    the labels in turn, every later one `rest`."""
     i = seen.get(name, 0)
     seen[name] = i + 1
-    return alternate[i % len(alternate)] if alternate else ""
+    if not alternate:
+        return ""
+    if isinstance(alternate, tuple):
+        labels, n, rest = alternate
+        return labels[i % len(labels)] if i < n else rest
+    return alternate[i % len(alternate)]
 
 
-def _labels_for(name: str, a) -> list[str] | None:
+def _labels_for(name: str, a):
     """The labels dealt to this kernel's dispatches: from --alternate-spec
-    ("SUBSTR=LABEL,LABEL;..."), else --alternate with --alternate-kernel."""
+    ("SUBSTR=LABEL,LABEL;..." or "SUBSTR=LABEL,LABEL@N,REST": the first N
+    dispatches in turn, then REST), else --alternate with --alternate-kernel."""
     for part in filter(None, (getattr(a, "alternate_spec", "") or "").split(";")):
         key, labels = part.split("=", 1)
         if key in name:
+            if "@" in labels:
+                cyc, tail = labels.split("@", 1)
+                n, rest = tail.split(",", 1)
+                return (cyc.split(","), int(n), rest)
             return labels.split(",")
     if a.alternate and a.alternate_kernel and a.alternate_kernel in name:
         return a.alternate.split(",")

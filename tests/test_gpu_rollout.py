@@ -118,7 +118,9 @@ def test_autograd_function_backward(gpu_lib):
 def test_kept_step_reverse_mode_equals_the_whole_entry(workload, n, precision, gpu_lib):
     """dsim_step_keep then dsim_vjp_kept run the same launches as
     dsim_step_vjp, so every output is bitwise the same; two reverse passes
-    read one kept step; DiffStep with keep gives the same gradients."""
+    read one kept step; dsim_jacobian_kept on the same kept step equals
+    dsim_step_jacobian bitwise; DiffStep with keep gives the same
+    gradients."""
     import torch
     from paper_2409_07107_amd import dsim
     from paper_2409_07107_amd.autograd import diff_step
@@ -140,6 +142,17 @@ def test_kept_step_reverse_mode_equals_the_whole_entry(workload, n, precision, g
         assert torch.equal(r1[k], whole[k]), k
         assert torch.equal(r2[k], whole2[k]), k
     assert torch.equal(r1["status"], whole["status"])
+    try:
+        full = dsim.step_jacobian(db)
+    except dsim.DsimError as exc:  # a derivative layout too large for the chip
+        assert "-2" in str(exc)
+        with pytest.raises(dsim.DsimError, match="-2"):
+            dsim.jacobian_kept(db, kept)
+    else:
+        jk = dsim.jacobian_kept(db, kept)
+        torch.cuda.synchronize()
+        for k in ("dvdq", "dvdv", "dvdtau", "status"):
+            assert torch.equal(jk[k], full[k]), k
     grads = []
     for keep in (False, True):
         q = db.q.clone().requires_grad_(True)
