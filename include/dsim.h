@@ -165,7 +165,8 @@ typedef struct dsim_params {
                              natural map, then ADMM, in FP64; Section II.B) */
     int32_t newton_iters; /* Newton iterations per refinement (>= 0) */
     int32_t threads;      /* threads per environment team: 64, 128, 256 or 512 (0 = auto: 128, and
-                             512 for the derivative launch when max_dofs >= 24) */
+                             512 for the derivative launch when max_dofs >= 24; 64 for the
+                             derivative entries' contact-solve and fallback launches) */
     double ncp_tol;       /* relative natural-map residual tolerance */
     double rank_tol;      /* relative pivot tolerance of the reduced factorisation */
     double mode_eps;      /* relative threshold of the mode classification */

@@ -101,9 +101,13 @@ size_t team_bytes(const dsim_batch* b, const dsim_params* p, int entry) {
 // compute unit, its LDS being the limit) is dense products that a larger team
 // spreads.  Measured on tree36 x 16384: FP32 19.5 ms with 128 threads,
 // 16.4 ms with 256, 14.9 ms with 512; FP64 17.7, 17.0 and 14.8 ms.  The
-// NCP launch of a derivative entry (the contact solve alone, from the
-// record) uses one wavefront: its team-wide phases are short loops over the
-// contact rows.
+// NCP and FBK launches of a derivative entry (the contact solve and its
+// fallback, from the record) use one wavefront unless the caller sets a
+// team size: their team-wide phases are short loops over the contact rows,
+// and where ten teams share a compute unit more wavefronts only wait.  (For
+// a batch whose largest environment leaves room for three teams per compute
+// unit, 256 threads measured faster: 104 against 119 ms per call on the
+// ragged batch, whose planner sets the team size.)
 int team_threads(const dsim_params* p, const dsim_batch* b, int entry) {
     if (p->threads > 0) return p->threads;
     if (entry == ENTRY_NCP || entry == ENTRY_FBK) return 64;
