@@ -413,6 +413,37 @@ int32_t dsim_step_integrate_vjp(const dsim_batch* batch, const dsim_params* para
                                 void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * dsim_step_integrate_vjp in two calls, for a rollout's reverse sweep over a
+ * recomputed segment: the step and position update as dsim_step_integrate
+ * (same outputs, bit for bit) that also keeps, in `ws`, the hand-over its
+ * adjoint reads (ws_bytes at least dsim_workspace_bytes for
+ * DSIM_ENTRY_STEP_INTEGRATE_VJP; DSIM_ERR_WORKSPACE otherwise, and
+ * DSIM_ERR_SIZE for a tree whose adjoint does not fit on chip, both before
+ * any launch) ...
+ */
+int32_t dsim_step_integrate_keep(const dsim_batch* batch, const dsim_params* params,
+                                 const void* q, const void* v, const void* tau,
+                                 void* q_next, void* v_next, void* lam, int8_t* mode, int32_t* status,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * ... then the adjoint of that step (Section III.A chained with the position
+ * update) without solving it again: a_q, a_v, g_tau as
+ * dsim_step_integrate_vjp computes them, bit for bit, for the same batch,
+ * params, q, v and tau, reading the kept hand-over from `ws` and the step's
+ * modes from `mode` (its output, unchanged); `status` is the step's status
+ * output, to which DSIM_ST_NONFINITE is added if an adjoint is not finite.
+ * One launch on `stream`, ordered after the keeping call; `ws` must not be
+ * written in between.
+ */
+int32_t dsim_step_integrate_vjp_kept(const dsim_batch* batch, const dsim_params* params,
+                                     const void* q, const void* v, const void* tau,
+                                     const void* a_qnext, const void* a_vnext,
+                                     const int8_t* mode, int32_t* status,
+                                     void* a_q, void* a_v, void* g_tau,
+                                     void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Maps a gradient in the tangent coordinates of q (g_tangent [sum n_v], as
  * returned by the VJP entries) to the stored coordinates of q
  * (g_ambient [sum n_q]): revolute entries copy; a free flyer gets

@@ -436,6 +436,25 @@ int dispatch(const dsim_batch* b, const dsim_params* p, const void* q, const voi
                                  ws, ws_bytes, stream, fork);
 }
 
+// The step and the position update (the step kernel's two launches, as the
+// step-only entry runs them) that also write the hand-over record and the
+// FP64 impulses into `ws`, for a later reverse pass through
+// dsim_step_integrate_vjp_kept.
+template <class R>
+int keep_integrate(const dsim_batch* b, const dsim_params* p, const void* q, const void* v, const void* tau,
+                   void* q_next, void* v_next, void* lam, int8_t* mode, int32_t* status, void* ws, size_t ws_bytes,
+                   void* stream) {
+    if (!ws || ws_bytes < handover_bytes(b, p)) return DSIM_ERR_WORKSPACE;
+    if (team_bytes(b, p, ENTRY_RVJP) > kLdsLimit) return DSIM_ERR_SIZE;  // its reverse pass must fit as well
+    double* ld = static_cast<double*>(ws);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int rc = launch_one<R, ENTRY_SINT>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, q_next,
+                                                 nullptr, nullptr, nullptr, nullptr, ld, stream, pass);
+        if (rc) return rc;
+    }
+    return DSIM_SUCCESS;
+}
+
 std::mutex g_scratch_mutex;
 void* g_scratch_ptr[kMaxDevices] = {};
 
@@ -735,6 +754,34 @@ int32_t dsim_step_integrate_vjp(const dsim_batch* b, const dsim_params* p, const
     if (!a_qnext || !a_vnext || !a_q || !a_v || !g_tau) return DSIM_ERR_ARG;
     return dispatch<ENTRY_RVJP>(b, p, q, v, tau, a_vnext, a_qnext, v_next, lam, mode, status, a_q, a_v, g_tau,
                                 nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int32_t dsim_step_integrate_keep(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                                 const void* tau, void* q_next, void* v_next, void* lam, int8_t* mode,
+                                 int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !v || !tau || !q_next || !v_next || !status || !mode || !lam) return DSIM_ERR_ARG;
+    if (p->precision == DSIM_F32)
+        return keep_integrate<float>(b, p, q, v, tau, q_next, v_next, lam, mode, status, ws, ws_bytes, stream);
+    return keep_integrate<double>(b, p, q, v, tau, q_next, v_next, lam, mode, status, ws, ws_bytes, stream);
+}
+
+int32_t dsim_step_integrate_vjp_kept(const dsim_batch* b, const dsim_params* p, const void* q, const void* v,
+                                     const void* tau, const void* a_qnext, const void* a_vnext, const int8_t* mode,
+                                     int32_t* status, void* a_q, void* a_v, void* g_tau, void* ws, size_t ws_bytes,
+                                     void* stream) {
+    int rc = check_common(b, p);
+    if (rc) return rc;
+    if (b->n_env == 0) return DSIM_SUCCESS;
+    if (!q || !v || !tau || !status || !mode || !a_qnext || !a_vnext || !a_q || !a_v || !g_tau) return DSIM_ERR_ARG;
+    int8_t* md = const_cast<int8_t*>(mode);  // read only by the derivative launch
+    if (p->precision == DSIM_F32)
+        return launch_half<float, ENTRY_RVJP>(2, b, p, q, v, tau, a_vnext, a_qnext, nullptr, nullptr, md, status, a_q,
+                                              a_v, g_tau, ws, ws_bytes, stream);
+    return launch_half<double, ENTRY_RVJP>(2, b, p, q, v, tau, a_vnext, a_qnext, nullptr, nullptr, md, status, a_q,
+                                           a_v, g_tau, ws, ws_bytes, stream);
 }
 
 int32_t dsim_tangent_to_ambient(const dsim_batch* b, int32_t precision, const void* q, const void* g_tangent,

@@ -29,7 +29,8 @@ SYMBOLS = ("dsim_default_params", "dsim_abi_version", "dsim_error_string", "dsim
            "dsim_step_jacobian", "dsim_step_vjp", "dsim_step_integrate", "dsim_step_integrate_vjp",
            "dsim_tangent_to_ambient", "dsim_struct_size", "dsim_step_vjp_params",
            "dsim_step_jacobian_params", "dsim_ambient_to_tangent", "dsim_status_string",
-           "dsim_step_keep", "dsim_vjp_kept", "dsim_jacobian_kept", "dsim_step_vjp_noalloc",
+           "dsim_step_keep", "dsim_vjp_kept", "dsim_jacobian_kept", "dsim_step_integrate_keep",
+           "dsim_step_integrate_vjp_kept", "dsim_step_vjp_noalloc",
            "dsim_noalloc_scratch_bytes")
 
 _vp = ctypes.c_void_p
@@ -96,6 +97,12 @@ def lib():
         L.dsim_jacobian_kept.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + \
             [_vp, ctypes.c_size_t, _vp]
         L.dsim_jacobian_kept.restype = ctypes.c_int32
+        L.dsim_step_integrate_keep.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 8 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_integrate_keep.restype = ctypes.c_int32
+        L.dsim_step_integrate_vjp_kept.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 10 + \
+            [_vp, ctypes.c_size_t, _vp]
+        L.dsim_step_integrate_vjp_kept.restype = ctypes.c_int32
         L.dsim_step_vjp_noalloc.argtypes = [ctypes.POINTER(CBatch), ctypes.POINTER(CParams)] + [_vp] * 13
         L.dsim_step_vjp_noalloc.restype = ctypes.c_int32
         L.dsim_noalloc_scratch_bytes.argtypes = []
@@ -573,6 +580,49 @@ def step_integrate_vjp(db: DeviceBatch, a_qnext, a_vnext, q=None, v=None, tau=No
                                          _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
                                          _ptr(out["a_q"]), _ptr(out["a_v"]), _ptr(out["g_tau"]), _ptr(ws),
                                          ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))
+    return out
+
+
+def step_integrate_keep(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, cb=None):
+    """dsim_step_integrate_keep: step_integrate's outputs plus the hand-over
+    its adjoint reads, in a fresh workspace tensor out["kept"] (held until
+    the reverse pass through step_integrate_vjp_kept is done)."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    out = _outputs(db)
+    out["q_next"] = torch.empty_like(q)
+    c = db.c if cb is None else cb
+    nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(c), ctypes.byref(p), ENTRY_STEP_INTEGRATE_VJP))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=db.device)
+    _check(lib().dsim_step_integrate_keep(ctypes.byref(c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                                          _ptr(out["q_next"]), _ptr(out["v_next"]), _ptr(out["lam"]),
+                                          _ptr(out["mode"]), _ptr(out["status"]), _ptr(ws), ctypes.c_size_t(nbytes),
+                                          ctypes.c_void_p(_stream())))
+    out["kept"] = ws
+    return out
+
+
+def step_integrate_vjp_kept(db: DeviceBatch, kept, a_qnext, a_vnext, q=None, v=None, tau=None,
+                            p: CParams | None = None, cb=None):
+    """dsim_step_integrate_vjp_kept: the adjoint of the kept step (the output
+    of step_integrate_keep for the same q, v, tau and params) without solving
+    it again: "a_q" (tangent), "a_v", "g_tau" and the step's "status"."""
+    import torch
+    p = p or db.params()
+    q = db.q if q is None else q
+    v = db.v if v is None else v
+    tau = db.tau if tau is None else tau
+    c = db.c if cb is None else cb
+    out = {k: torch.empty(db.n_dof, dtype=db.dtype, device=db.device) for k in ("a_q", "a_v", "g_tau")}
+    out["status"] = kept["status"].clone()
+    ws = kept["kept"]
+    _check(lib().dsim_step_integrate_vjp_kept(ctypes.byref(c), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
+                                              _ptr(a_qnext), _ptr(a_vnext), _ptr(kept["mode"]), _ptr(out["status"]),
+                                              _ptr(out["a_q"]), _ptr(out["a_v"]), _ptr(out["g_tau"]), _ptr(ws),
+                                              ctypes.c_size_t(ws.numel()), ctypes.c_void_p(_stream())))
     return out
 
 

@@ -8,7 +8,12 @@ state with respect to every torque is accumulated in reverse with one
 `dsim_step_integrate_vjp` launch per step.  Only the states at every
 `checkpoint`-th step are kept on the forward pass; each segment is recomputed
 from its checkpoint before its reverse sweep, so memory is
-O(T / checkpoint + checkpoint) states instead of O(T).
+O(T / checkpoint + checkpoint) states instead of O(T).  With `keep` (the
+default) the recomputation keeps each step's hand-over
+(`dsim_step_integrate_keep`, about 41 KB per 36-dof environment and step of
+the segment) and the reverse sweep runs the adjoint alone
+(`dsim_step_integrate_vjp_kept`) instead of solving each step a third time;
+the gradients are bitwise the same.
 """
 from __future__ import annotations
 
@@ -30,14 +35,15 @@ def rollout(db, q0, v0, taus, p=None):
     return q, v, status
 
 
-def rollout_gradient(db, q0, v0, taus, loss_fn, checkpoint=20, p=None, state_adjoint=None):
+def rollout_gradient(db, q0, v0, taus, loss_fn, checkpoint=20, p=None, state_adjoint=None, keep=True):
     """Loss on the final state and its gradient with respect to taus
     (T x sum n_v).  `loss_fn(q_T, v_T)` returns (loss per env, tangent adjoint
     of q_T [sum n_v], adjoint of v_T [sum n_v]).  `state_adjoint(t, q_t, v_t)`
     (optional) returns the adjoints (tangent on q, on v) of a loss term on an
     intermediate state t = 1 .. T-1, or None.  Returns (loss, grad_taus,
     info) with info holding q_T, v_T, the OR of all status words and the
-    adjoints of the initial state."""
+    adjoints of the initial state.  `keep` selects the reverse sweep from
+    kept hand-overs (see the module docstring) or from re-solved steps."""
     p = p or db.params()
     T = int(taus.shape[0])
     C = max(1, int(checkpoint))
@@ -55,13 +61,27 @@ def rollout_gradient(db, q0, v0, taus, loss_fn, checkpoint=20, p=None, state_adj
     for s0 in reversed(range(0, T, C)):
         s1 = min(s0 + C, T)
         qs, vs = [ckpt[s0][0]], [ckpt[s0][1]]
-        for t in range(s0, s1 - 1):  # recompute the segment's states
-            o = dsim.step_integrate(db, qs[-1], vs[-1], taus[t], p)
-            qs.append(o["q_next"])
-            vs.append(o["v_next"])
+        kept = []
+        if keep:  # recompute the segment, keeping every step's hand-over
+            for t in range(s0, s1):
+                o = dsim.step_integrate_keep(db, qs[-1], vs[-1], taus[t], p)
+                kept.append(o)
+                if t < s1 - 1:
+                    qs.append(o["q_next"])
+                    vs.append(o["v_next"])
+        else:  # recompute the segment's states
+            for t in range(s0, s1 - 1):
+                o = dsim.step_integrate(db, qs[-1], vs[-1], taus[t], p)
+                qs.append(o["q_next"])
+                vs.append(o["v_next"])
         for t in reversed(range(s0, s1)):
             i = t - s0
-            o = dsim.step_integrate_vjp(db, a_q.contiguous(), a_v.contiguous(), qs[i], vs[i], taus[t], p)
+            if keep:
+                o = dsim.step_integrate_vjp_kept(db, kept[i], a_q.contiguous(), a_v.contiguous(), qs[i], vs[i],
+                                                 taus[t], p)
+                kept[i] = None  # its workspace is free once the adjoint is enqueued
+            else:
+                o = dsim.step_integrate_vjp(db, a_q.contiguous(), a_v.contiguous(), qs[i], vs[i], taus[t], p)
             a_q, a_v = o["a_q"], o["a_v"]
             grads[t] = o["g_tau"]
             if state_adjoint is not None and t > 0:

@@ -259,6 +259,46 @@ def test_checkpointing_does_not_change_the_gradient(gpu_lib):
     assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
 
 
+@pytest.mark.parametrize("workload,n,precision", [("tree36", 32, 1), ("tree36", 32, 0), ("mixed", 48, 1)])
+def test_kept_rollout_steps_equal_the_whole_entries(workload, n, precision, gpu_lib):
+    """dsim_step_integrate_keep equals dsim_step_integrate and, on its kept
+    hand-over, dsim_step_integrate_vjp_kept equals dsim_step_integrate_vjp,
+    bit for bit; the rollout gradient from kept hand-overs equals the one
+    that solves each step again, bit for bit, loss and initial-state
+    adjoints included."""
+    import torch
+    from paper_2409_07107_amd import dsim, rollout
+    batch = scenes.make(workload, n, seed=9)
+    db = _db(batch, precision)
+    rng = np.random.default_rng(3)
+    a_q = torch.as_tensor(rng.normal(size=db.n_dof), dtype=db.dtype, device=db.device)
+    a_v = torch.as_tensor(rng.normal(size=db.n_dof), dtype=db.dtype, device=db.device)
+    plain = dsim.step_integrate(db)
+    kept = dsim.step_integrate_keep(db)
+    whole = dsim.step_integrate_vjp(db, a_q, a_v)
+    adj = dsim.step_integrate_vjp_kept(db, kept, a_q, a_v)
+    torch.cuda.synchronize()
+    for k in ("q_next", "v_next", "lam", "mode", "status"):
+        assert torch.equal(kept[k], plain[k]), k
+    for k in ("a_q", "a_v", "g_tau"):
+        assert torch.equal(adj[k], whole[k]), k
+    assert torch.equal(adj["status"], whole["status"])
+    T = 9
+    tt = torch.as_tensor(rng.normal(scale=0.3, size=(T, db.n_dof)), dtype=db.dtype, device=db.device)
+    w = torch.as_tensor(rng.normal(size=db.n_dof), dtype=db.dtype, device=db.device)
+
+    def lf(q, v):  # a linear loss on the final velocities (any tree, with or without a free root)
+        return (v * w).sum().reshape(1), torch.zeros_like(w), w.clone()
+
+    r_keep = rollout.rollout_gradient(db, db.q, db.v, tt, lf, checkpoint=4, keep=True)
+    r_solve = rollout.rollout_gradient(db, db.q, db.v, tt, lf, checkpoint=4, keep=False)
+    torch.cuda.synchronize()
+    assert torch.equal(r_keep[0], r_solve[0])
+    assert torch.equal(r_keep[1], r_solve[1])
+    for k in ("q", "v", "status", "a_q0", "a_v0"):
+        assert torch.equal(r_keep[2][k], r_solve[2][k]), k
+
+
 def test_long_rollout_directional_derivative(gpu_lib):
     """Property at rollout length: the FP64 gradient agrees with central
     differences (h = 1e-6) of the FP64 forward rollout along a random torque

@@ -148,10 +148,17 @@ def test_short_workspace_is_rejected_before_any_launch(L):
         assert L.dsim_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), None, need, None) == -4
         assert L.dsim_jacobian_kept(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 8), dummy, need - 1, None) == -4
         assert L.dsim_jacobian_kept(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 8), None, need, None) == -4
+        assert L.dsim_step_integrate_keep(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 8), dummy, need - 1,
+                                          None) == -4
+        assert L.dsim_step_integrate_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([dummy] * 10), dummy, need - 1,
+                                              None) == -4
         # and rejects missing arrays
         assert L.dsim_step_keep(ctypes.byref(cb), ctypes.byref(p), *([None] * 7), dummy, need, None) == -1
         assert L.dsim_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([None] * 10), dummy, need, None) == -1
         assert L.dsim_jacobian_kept(ctypes.byref(cb), ctypes.byref(p), *([None] * 8), dummy, need, None) == -1
+        assert L.dsim_step_integrate_keep(ctypes.byref(cb), ctypes.byref(p), *([None] * 8), dummy, need, None) == -1
+        assert L.dsim_step_integrate_vjp_kept(ctypes.byref(cb), ctypes.byref(p), *([None] * 10), dummy, need,
+                                              None) == -1
 
 
 def test_on_chip_sizing(L):
