@@ -236,7 +236,14 @@ size_t dsim_lds_bytes(const dsim_batch* batch, const dsim_params* params, int32_
  * Runs as two launches on `stream`: the solve's first pass over every
  * environment, then its fallback pass, which reads the first pass's lam and
  * status for the environments left unsolved (so the output buffers must not
- * alias the inputs).
+ * alias the inputs).  The workspace is optional: given one of at least
+ * dsim_workspace_bytes(batch, params, DSIM_ENTRY_JACOBIAN) bytes, the step
+ * runs as the derivative entries' step launches (the first pass as an
+ * assembly launch and a contact-solve launch in a smaller on-chip layout,
+ * then the fallback pass from the record they leave in `ws`): the same
+ * outputs bit for bit, faster on large batches, and `ws` then holds the
+ * FP64 impulses and solver counts described below.  NULL, or fewer bytes,
+ * selects the two launches.
  */
 int32_t dsim_step(const dsim_batch* batch, const dsim_params* params,
                   const void* q, const void* v, const void* tau,

@@ -359,6 +359,15 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
            const void* gbar, const void* gbar2, void* v_next, void* lam, int8_t* mode, int32_t* status, void* o1,
            void* o2, void* o3, void* o4, void* o5, void* ws, size_t ws_bytes, void* stream, bool fork) {
     if (b->n_env == 0) return DSIM_SUCCESS;
+    if (ENTRY == ENTRY_STEP && ws && ws_bytes >= handover_bytes(b, p)) {
+        // the step with a workspace: the derivative entries' step launches
+        // (the same outputs, bit for bit; more teams iterate per compute unit)
+        double* ld = static_cast<double*>(ws);
+        int rc = first_pass<R>(b, p, q, v, tau, v_next, lam, mode, status, ld, stream);
+        if (rc) return rc;
+        return launch_one<R, ENTRY_FBK>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
+    }
     if (!entry_has_derivative(ENTRY)) {
         int rc = launch_one<R, ENTRY>(b, p, q, v, tau, gbar, gbar2, v_next, lam, mode, status, o1, o2, o3, o4, o5,
                                       nullptr, stream, 0);

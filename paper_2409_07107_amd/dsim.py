@@ -254,16 +254,18 @@ class DeviceBatch:
         p.kd = float(overrides.get("kd", getattr(self.batch, "kd", 0.0)))
         return p
 
-    def workspace(self, p: CParams, entry: int, cb=None):
+    def workspace(self, p: CParams, entry: int, cb=None, tag=None):
         """The workspace of an entry (one per concurrent slot, see
-        private_workspace), sized for the launch's batch struct `cb` (a size
-        class of this batch) or for the whole batch."""
+        private_workspace, and per `tag`: the step entry keeps its own, so
+        that solver_work reads the derivative entries' last call), sized for
+        the launch's batch struct `cb` (a size class of this batch) or for
+        the whole batch."""
         import torch
         c = self.c if cb is None else cb
         nbytes = int(lib().dsim_workspace_bytes(ctypes.byref(c), ctypes.byref(p), int(entry)))
         if nbytes == 0:
             return None, 0
-        key = (self._slot, nbytes)
+        key = (self._slot, nbytes, tag)
         if key not in self._ws:
             self._ws[key] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self._ws[key], nbytes
@@ -304,14 +306,17 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None):
-    """v+, impulses, modes and status of one step for every environment."""
+def step(db: DeviceBatch, q=None, v=None, tau=None, p: CParams | None = None, out=None, cb=None, split=True):
+    """v+, impulses, modes and status of one step for every environment.
+    With `split` the call passes a workspace (its own, not the derivative
+    entries') and dsim_step runs as the derivative entries' step launches;
+    the outputs are bitwise the same either way."""
     p = p or db.params()
     q = db.q if q is None else q
     v = db.v if v is None else v
     tau = db.tau if tau is None else tau
     out = out or _outputs(db)
-    ws, nbytes = db.workspace(p, ENTRY_STEP, cb)
+    ws, nbytes = db.workspace(p, ENTRY_JACOBIAN if split else ENTRY_STEP, cb, tag="step")
     _check(lib().dsim_step(ctypes.byref(db.c if cb is None else cb), ctypes.byref(p), _ptr(q), _ptr(v), _ptr(tau),
                            _ptr(out["v_next"]), _ptr(out["lam"]), _ptr(out["mode"]), _ptr(out["status"]),
                            _ptr(ws), ctypes.c_size_t(nbytes), ctypes.c_void_p(_stream())))

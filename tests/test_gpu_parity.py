@@ -105,6 +105,23 @@ def test_step_only_matches_jacobian_entry(gpu_lib):
     assert torch.equal(a["status"], b["status"])
 
 
+@pytest.mark.parametrize("workload,n,precision", [("tree36", 2048, 1), ("tree36", 512, 0), ("arm7", 1024, 0),
+                                                  ("mixed", 256, 1)])
+def test_step_with_and_without_workspace(workload, n, precision, gpu_lib):
+    """dsim_step given a workspace runs the derivative entries' step launches
+    (assembly, contact solve, fallback pass from the record); without one,
+    the two launches of the step kernel: every output bitwise the same."""
+    import torch
+    from paper_2409_07107_amd import dsim
+    batch = scenes.make(workload, n, seed=21)
+    db = dsim.DeviceBatch(batch, precision=precision)
+    a = dsim.step(db, split=True)
+    b = dsim.step(db, split=False)
+    torch.cuda.synchronize()
+    for k in ("v_next", "lam", "mode", "status"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_empty_batch_and_no_contacts(gpu_lib):
     import torch
     from paper_2409_07107_amd import dsim
