@@ -29,8 +29,9 @@
  * params->precision == DSIM_F32 and double when DSIM_F64; index arrays are
  * int32.  Buffers must stay valid until the work on `stream` has completed.
  * `stream` is a hipStream_t (NULL = the default stream); all compute calls are
- * asynchronous on it.  The derivative entries (outside graph capture, and
- * except dsim_step_vjp_noalloc) run part of their work on a second stream
+ * asynchronous on it.  The derivative entries (outside graph capture, for a
+ * batch without a launch list, and except dsim_step_vjp_noalloc) run part of
+ * their work on a second stream
  * that the library creates once per device (default priority), forked from
  * and joined back to `stream` with events: the call's work is complete, and
  * its outputs ready, in `stream`'s order as for any other call.

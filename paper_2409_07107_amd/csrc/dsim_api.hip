@@ -381,7 +381,11 @@ int launch(const dsim_batch* b, const dsim_params* p, const void* q, const void*
     int rc = first_pass<R>(b, p, q, v, tau, v_next, lam, mode, status, ld, stream);
     if (rc) return rc;
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    SideStream* side = fork ? side_stream(s) : nullptr;
+    // a launch list (a plan's size class, whose caller runs the classes on
+    // streams of its own) keeps its launches on the caller's stream: the
+    // classes would otherwise queue their fallback passes on the one second
+    // stream
+    SideStream* side = (fork && !b->order) ? side_stream(s) : nullptr;
     if (!side) {
         rc = launch_one<R, ENTRY_FBK>(b, p, q, v, tau, nullptr, nullptr, v_next, lam, mode, status, nullptr,
                                       nullptr, nullptr, nullptr, nullptr, ld, stream, 1);
